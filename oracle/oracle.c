@@ -1,0 +1,615 @@
+/*
+ * oracle.c -- CPU oracle for the Chemora right-hand-side path.
+ *
+ * TEST INFRASTRUCTURE ONLY: the product library never includes, links or
+ * calls this file.  It is the plain definition that the HIP path is checked
+ * against, written from the paper and from the standard BSSN literature the
+ * paper builds on, in FP64 with no blocking, fusion or reordering:
+ *
+ *   - the time-evolution right-hand side of a PDE system evaluated by finite
+ *     differences on a uniform block with ghost zones (Sec. III "Efficient
+ *     collaborations vs. efficient code", eq. (1); Sec. III.B.2
+ *     "Discretisation description": standard centred finite-difference
+ *     operators, here of 4th order);
+ *   - the scalar wave system in the two-variable reading du/dt = rho,
+ *     drho/dt = Laplacian(u) (eq. (1) with v_i = d_i u eliminated);
+ *   - the BSSN form of the Einstein equations that the paper evolves
+ *     (Sec. III.D "Single-node performance"; its cited formulation), in the
+ *     chi-variant with 1+log or harmonic slicing and a Gamma-driver or
+ *     frozen shift, advection terms by lopsided (upwinded) 4th-order stencils;
+ *   - ghost-zone filling, periodic or from the analytic gauge wave, and the
+ *     classical RK4 method of lines (Sec. II, the driver and time-integrator
+ *     thorns);
+ *   - the Hamiltonian and momentum constraints with FP64 RMS norms
+ *     (Sec. III.B.1 "Physics system description": constraints are part of a
+ *     physics system).
+ *
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp (no contraction,
+ * so every expression rounds in the order written).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <omp.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* geometry of one block                                                    */
+
+typedef struct {
+  int n[3], g, e[3];
+  long sy, sz, npts;
+} geom;
+
+static geom mkgeom(const orc_params* p) {
+  geom G;
+  G.g = p->g;
+  for (int d = 0; d < 3; d++) {
+    G.n[d] = p->n[d];
+    G.e[d] = p->n[d] + 2 * p->g;
+  }
+  G.sy = G.e[0];
+  G.sz = (long)G.e[0] * G.e[1];
+  G.npts = G.sz * G.e[2];
+  return G;
+}
+
+static long idx(const geom* G, int i, int j, int k) {
+  return (long)(i + G->g) + (long)(j + G->g) * G->sy + (long)(k + G->g) * G->sz;
+}
+
+static int is_interior(const geom* G, int i, int j, int k) {
+  return i >= 0 && i < G->n[0] && j >= 0 && j < G->n[1] && k >= 0 && k < G->n[2];
+}
+
+int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------ */
+/* 4th-order finite-difference operators (Sec. III.B.2: standard centred
+ * operators of a chosen order; the lopsided pair is the 4th-order
+ * one-sided-by-one-point stencil used for advection terms).
+ * f points at the centre value; s is the stride along the axis.            */
+
+static double fd1(const double* f, long s, double h) {
+  return (f[-2 * s] - 8.0 * f[-s] + 8.0 * f[s] - f[2 * s]) / (12.0 * h);
+}
+
+static double fd2(const double* f, long s, double h) {
+  return (-f[-2 * s] + 16.0 * f[-s] - 30.0 * f[0] + 16.0 * f[s] - f[2 * s]) /
+         (12.0 * h * h);
+}
+
+/* mixed derivative: product of the centred first-derivative stencil along
+ * both axes */
+static double fd11(const double* f, long sa, long sb, double ha, double hb) {
+  static const int off[4] = {-2, -1, 1, 2};
+  static const double w[4] = {1.0, -8.0, 8.0, -1.0};
+  double acc = 0.0;
+  for (int a = 0; a < 4; a++)
+    for (int b = 0; b < 4; b++) acc += w[a] * w[b] * f[off[a] * sa + off[b] * sb];
+  return acc / (144.0 * ha * hb);
+}
+
+/* lopsided first derivative, shifted one point towards the upwind side
+ * chosen by the sign of the advecting velocity */
+static double fdup(const double* f, long s, double h, double vel) {
+  if (vel >= 0.0)
+    return (-3.0 * f[-s] - 10.0 * f[0] + 18.0 * f[s] - 6.0 * f[2 * s] + f[3 * s]) /
+           (12.0 * h);
+  return (3.0 * f[s] + 10.0 * f[0] - 18.0 * f[-s] + 6.0 * f[-2 * s] - f[-3 * s]) /
+         (12.0 * h);
+}
+
+/* ------------------------------------------------------------------------ */
+/* ghost zones (Sec. II: the driver owns ghost zones)                       */
+
+/* periodic images: x first, then y over the x-extended range, then z over
+ * the xy-extended range, so edges and corners are filled too */
+void orc_fill_periodic(const orc_params* p, int nvar, double* f) {
+  geom G = mkgeom(p);
+  const int g = G.g, nx = G.n[0], ny = G.n[1], nz = G.n[2];
+  for (int v = 0; v < nvar; v++) {
+    double* a = f + v * G.npts;
+    for (int k = 0; k < nz; k++)
+      for (int j = 0; j < ny; j++)
+        for (int i = -g; i < 0; i++) a[idx(&G, i, j, k)] = a[idx(&G, i + nx, j, k)];
+    for (int k = 0; k < nz; k++)
+      for (int j = 0; j < ny; j++)
+        for (int i = nx; i < nx + g; i++) a[idx(&G, i, j, k)] = a[idx(&G, i - nx, j, k)];
+    for (int k = 0; k < nz; k++)
+      for (int i = -g; i < nx + g; i++) {
+        for (int j = -g; j < 0; j++) a[idx(&G, i, j, k)] = a[idx(&G, i, j + ny, k)];
+        for (int j = ny; j < ny + g; j++) a[idx(&G, i, j, k)] = a[idx(&G, i, j - ny, k)];
+      }
+    for (int j = -g; j < ny + g; j++)
+      for (int i = -g; i < nx + g; i++) {
+        for (int k = -g; k < 0; k++) a[idx(&G, i, j, k)] = a[idx(&G, i, j, k + nz)];
+        for (int k = nz; k < nz + g; k++) a[idx(&G, i, j, k)] = a[idx(&G, i, j, k - nz)];
+      }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* BSSN variable indices and the symmetric-pair map                         */
+
+enum { CHI = 0, GT = 1, TRK = 7, AT = 8, GAM = 14, ALP = 17, BETA = 18, BB = 21, NB = 24 };
+static const int SYM[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+
+/* Analytic gauge wave: the flat metric in coordinates where
+ * ds^2 = -H dt^2 + H dx_a^2 + (other axes)^2, H = 1 - A sin(2 pi (x_a - t)/d),
+ * with zero shift; an exact vacuum solution under harmonic slicing.  BSSN
+ * variables from its 3-metric gamma_aa = H and extrinsic curvature
+ * K_aa = -dt(gamma_aa)/(2 alpha).                                          */
+static void gaugewave_point(const orc_params* p, double xa, double t, double* v,
+                            long stride) {
+  const double A = p->gw_amp, d = p->gw_d;
+  const int a = p->gw_axis;
+  const double th = 2.0 * M_PI * (xa - t) / d;
+  const double H = 1.0 - A * sin(th), c = cos(th);
+  for (int q = 0; q < NB; q++) v[q * stride] = 0.0;
+  v[CHI * stride] = pow(H, -1.0 / 3.0);
+  for (int b = 0; b < 3; b++) {
+    v[(GT + SYM[b][b]) * stride] = (b == a) ? pow(H, 2.0 / 3.0) : pow(H, -1.0 / 3.0);
+    v[(AT + SYM[b][b]) * stride] =
+        (b == a) ? -(2.0 * M_PI * A / (3.0 * d)) * c * pow(H, -5.0 / 6.0)
+                 : (M_PI * A / (3.0 * d)) * c * pow(H, -11.0 / 6.0);
+  }
+  v[TRK * stride] = -(M_PI * A / d) * c * pow(H, -1.5);
+  v[(GAM + a) * stride] = -(4.0 * M_PI * A / (3.0 * d)) * c * pow(H, -5.0 / 3.0);
+  v[ALP * stride] = sqrt(H);
+}
+
+/* fill every ghost point of all 24 BSSN grid functions from the gauge wave
+ * evaluated at time t */
+void orc_fill_gaugewave(const orc_params* p, double t, double* y) {
+  geom G = mkgeom(p);
+  const int g = G.g, a = p->gw_axis;
+  for (int k = -g; k < G.n[2] + g; k++)
+    for (int j = -g; j < G.n[1] + g; j++)
+      for (int i = -g; i < G.n[0] + g; i++) {
+        if (is_interior(&G, i, j, k)) continue;
+        const int ii[3] = {i, j, k};
+        const double xa = p->origin[a] + ii[a] * p->h[a];
+        gaugewave_point(p, xa, t, y + idx(&G, i, j, k), G.npts);
+      }
+}
+
+static void fill_ghosts(const orc_params* p, int system, int bc, double t, double* y) {
+  if (system == ORC_BSSN && bc == ORC_BC_GAUGEWAVE)
+    orc_fill_gaugewave(p, t, y);
+  else
+    orc_fill_periodic(p, system == ORC_WAVE ? 2 : NB, y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scalar wave, eq. (1) in the two-variable reading:
+ *   du/dt = rho,  drho/dt = d_xx u + d_yy u + d_zz u                         */
+
+void orc_wave_rhs(const orc_params* p, const double* y, double* r) {
+  geom G = mkgeom(p);
+  const long st[3] = {1, G.sy, G.sz};
+  const double* u = y;
+  const double* rho = y + G.npts;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < G.n[2]; k++)
+    for (int j = 0; j < G.n[1]; j++)
+      for (int i = 0; i < G.n[0]; i++) {
+        const long q = idx(&G, i, j, k);
+        r[q] = rho[q];
+        r[G.npts + q] = fd2(u + q, st[0], p->h[0]) + fd2(u + q, st[1], p->h[1]) +
+                        fd2(u + q, st[2], p->h[2]);
+      }
+}
+
+/* ------------------------------------------------------------------------ */
+/* BSSN right-hand side at one interior point, in three phases:
+ *   1. every stencil (centred 1st, centred 2nd and mixed, lopsided advection)
+ *   2. the derived quantities (inverse metric, Christoffels, Ricci, ...)
+ *   3. the 24 right-hand sides.
+ * chi-form BSSN: chi = det(gamma)^(-1/3), gt_ij = chi gamma_ij,
+ * At_ij = chi (K_ij - gamma_ij K / 3); the evolved Gamt^i enters only through
+ * its derivatives (Ricci tensor) and its advection; everywhere else the
+ * contracted Christoffel symbols recomputed from gt_ij are used.            */
+
+static void bssn_point(const orc_params* p, const geom* G, const double* y, long q,
+                       double out[NB], double cons[4]) {
+  const long st[3] = {1, G->sy, G->sz};
+  const double* h = p->h;
+  double u[NB], d1[NB][3], d2[NB][3][3], adv[NB];
+
+  /* phase 1: stencils */
+  for (int v = 0; v < NB; v++) {
+    const double* f = y + v * G->npts + q;
+    u[v] = f[0];
+    for (int a = 0; a < 3; a++) d1[v][a] = fd1(f, st[a], h[a]);
+    for (int a = 0; a < 3; a++) {
+      d2[v][a][a] = fd2(f, st[a], h[a]);
+      for (int b = a + 1; b < 3; b++) {
+        d2[v][a][b] = fd11(f, st[a], st[b], h[a], h[b]);
+        d2[v][b][a] = d2[v][a][b];
+      }
+    }
+  }
+  const double beta[3] = {u[BETA], u[BETA + 1], u[BETA + 2]};
+  for (int v = 0; v < NB; v++) {
+    const double* f = y + v * G->npts + q;
+    adv[v] = 0.0;
+    for (int k = 0; k < 3; k++) adv[v] += beta[k] * fdup(f, st[k], h[k], beta[k]);
+  }
+
+  /* phase 2: derived quantities */
+  const double chi = u[CHI], trK = u[TRK], alpha = u[ALP];
+  double gt[3][3], At[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      gt[i][j] = u[GT + SYM[i][j]];
+      At[i][j] = u[AT + SYM[i][j]];
+    }
+  const double det = gt[0][0] * (gt[1][1] * gt[2][2] - gt[1][2] * gt[2][1]) -
+                     gt[0][1] * (gt[1][0] * gt[2][2] - gt[1][2] * gt[2][0]) +
+                     gt[0][2] * (gt[1][0] * gt[2][1] - gt[1][1] * gt[2][0]);
+  double gu[3][3]; /* inverse conformal metric: adjugate over determinant */
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      gu[i][j] = (gt[(j + 1) % 3][(i + 1) % 3] * gt[(j + 2) % 3][(i + 2) % 3] -
+                  gt[(j + 1) % 3][(i + 2) % 3] * gt[(j + 2) % 3][(i + 1) % 3]) /
+                 det;
+
+  /* dgt[i][j][k] = d_k gt_ij */
+  double dgt[3][3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) dgt[i][j][k] = d1[GT + SYM[i][j]][k];
+
+  /* Christoffels of the conformal metric: first index lowered, then raised */
+  double cdl[3][3][3], cdu[3][3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++)
+        cdl[i][j][k] = 0.5 * (dgt[i][k][j] + dgt[i][j][k] - dgt[j][k][i]);
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) {
+        double s = 0.0;
+        for (int l = 0; l < 3; l++) s += gu[i][l] * cdl[l][j][k];
+        cdu[i][j][k] = s;
+      }
+  double Gd[3]; /* contracted Christoffels recomputed from gt */
+  for (int i = 0; i < 3; i++) {
+    double s = 0.0;
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) s += gu[j][k] * cdu[i][j][k];
+    Gd[i] = s;
+  }
+
+  double dchi[3], dK[3], dalp[3], dbeta[3][3], dGam[3][3];
+  for (int a = 0; a < 3; a++) {
+    dchi[a] = d1[CHI][a];
+    dK[a] = d1[TRK][a];
+    dalp[a] = d1[ALP][a];
+  }
+  for (int k = 0; k < 3; k++)
+    for (int j = 0; j < 3; j++) {
+      dbeta[k][j] = d1[BETA + k][j]; /* d_j beta^k */
+      dGam[k][j] = d1[GAM + k][j];   /* d_j Gamt^k */
+    }
+  double divbeta = 0.0;
+  for (int k = 0; k < 3; k++) divbeta += dbeta[k][k];
+
+  /* conformal covariant second derivative of chi */
+  double DDchi[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0.0;
+      for (int k = 0; k < 3; k++) s += cdu[k][i][j] * dchi[k];
+      DDchi[i][j] = d2[CHI][i][j] - s;
+    }
+  double trDDchi = 0.0, dchi2 = 0.0;
+  for (int l = 0; l < 3; l++)
+    for (int m = 0; m < 3; m++) {
+      trDDchi += gu[l][m] * DDchi[l][m];
+      dchi2 += gu[l][m] * dchi[l] * dchi[m];
+    }
+
+  /* Ricci tensor: conformal part plus chi part */
+  double R[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0;
+      for (int l = 0; l < 3; l++)
+        for (int m = 0; m < 3; m++) t1 += gu[l][m] * d2[GT + SYM[i][j]][l][m];
+      t1 = -0.5 * t1;
+      for (int k = 0; k < 3; k++) t2 += gt[k][i] * dGam[k][j] + gt[k][j] * dGam[k][i];
+      t2 = 0.5 * t2;
+      for (int k = 0; k < 3; k++) t3 += Gd[k] * (cdl[i][j][k] + cdl[j][i][k]);
+      t3 = 0.5 * t3;
+      for (int l = 0; l < 3; l++)
+        for (int m = 0; m < 3; m++) {
+          double s = 0.0;
+          for (int k = 0; k < 3; k++)
+            s += cdu[k][l][i] * cdl[j][k][m] + cdu[k][l][j] * cdl[i][k][m] +
+                 cdu[k][i][m] * cdl[k][l][j];
+          t4 += gu[l][m] * s;
+        }
+      const double Rt = t1 + t2 + t3 + t4;
+      const double Rchi = (DDchi[i][j] + gt[i][j] * trDDchi) / (2.0 * chi) -
+                          (dchi[i] * dchi[j] + 3.0 * gt[i][j] * dchi2) / (4.0 * chi * chi);
+      R[i][j] = Rt + Rchi;
+    }
+  double Rsc = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) Rsc += gu[i][j] * R[i][j];
+  Rsc = chi * Rsc;
+
+  /* physical Christoffels and the covariant second derivative of the lapse */
+  double DDalp[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0.0;
+      for (int k = 0; k < 3; k++) {
+        double gul = 0.0;
+        for (int l = 0; l < 3; l++) gul += gu[k][l] * dchi[l];
+        const double dik = (k == i) ? 1.0 : 0.0, djk = (k == j) ? 1.0 : 0.0;
+        const double Gphys =
+            cdu[k][i][j] - (dik * dchi[j] + djk * dchi[i] - gt[i][j] * gul) / (2.0 * chi);
+        s += Gphys * dalp[k];
+      }
+      DDalp[i][j] = d2[ALP][i][j] - s;
+    }
+  double lapalp = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) lapalp += gu[i][j] * DDalp[i][j];
+  lapalp = chi * lapalp;
+
+  /* traceless extrinsic curvature with indices raised by gu */
+  double Atm[3][3], Atu[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0.0;
+      for (int k = 0; k < 3; k++) s += gu[i][k] * At[k][j];
+      Atm[i][j] = s; /* At^i_j */
+    }
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0.0;
+      for (int k = 0; k < 3; k++) s += Atm[i][k] * gu[k][j];
+      Atu[i][j] = s; /* At^ij */
+    }
+  double AtAt = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) AtAt += Atm[i][j] * Atm[j][i];
+
+  /* trace-free part of -D_i D_j alpha + alpha R_ij */
+  double X[3][3], trX = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) X[i][j] = -DDalp[i][j] + alpha * R[i][j];
+  for (int k = 0; k < 3; k++)
+    for (int l = 0; l < 3; l++) trX += gu[k][l] * X[k][l];
+
+  if (cons) {
+    /* Hamiltonian and momentum constraints (centred stencils only) */
+    cons[0] = Rsc + (2.0 / 3.0) * trK * trK - AtAt;
+    for (int i = 0; i < 3; i++) {
+      double s = 0.0;
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++)
+          for (int j = 0; j < 3; j++) {
+            double DAt = d1[AT + SYM[a][b]][j];
+            for (int m = 0; m < 3; m++) DAt -= cdu[m][j][a] * At[m][b] + cdu[m][j][b] * At[a][m];
+            s += gu[i][a] * gu[j][b] * DAt;
+          }
+      double s2 = 0.0, s3 = 0.0;
+      for (int j = 0; j < 3; j++) {
+        s2 += gu[i][j] * dK[j];
+        s3 += Atu[i][j] * dchi[j];
+      }
+      cons[1 + i] = s - (2.0 / 3.0) * s2 - 1.5 * s3 / chi;
+    }
+  }
+  if (!out) return;
+
+  /* phase 3: right-hand sides */
+  out[CHI] = adv[CHI] + (2.0 / 3.0) * chi * (alpha * trK - divbeta);
+  for (int i = 0; i < 3; i++)
+    for (int j = i; j < 3; j++) {
+      double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int k = 0; k < 3; k++) {
+        s1 += gt[i][k] * dbeta[k][j];
+        s2 += gt[j][k] * dbeta[k][i];
+        s3 += At[i][k] * Atm[k][j];
+      }
+      out[GT + SYM[i][j]] =
+          adv[GT + SYM[i][j]] - 2.0 * alpha * At[i][j] + s1 + s2 - (2.0 / 3.0) * gt[i][j] * divbeta;
+      double a1 = 0.0, a2 = 0.0;
+      for (int k = 0; k < 3; k++) {
+        a1 += At[i][k] * dbeta[k][j];
+        a2 += At[j][k] * dbeta[k][i];
+      }
+      const double XTF = X[i][j] - gt[i][j] * trX / 3.0;
+      out[AT + SYM[i][j]] = adv[AT + SYM[i][j]] + chi * XTF +
+                            alpha * (trK * At[i][j] - 2.0 * s3) + a1 + a2 -
+                            (2.0 / 3.0) * At[i][j] * divbeta;
+    }
+  out[TRK] = adv[TRK] - lapalp + alpha * (AtAt + trK * trK / 3.0);
+
+  double Gnoadv[3];
+  for (int i = 0; i < 3; i++) {
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0, s6 = 0.0, s7 = 0.0;
+    for (int k = 0; k < 3; k++) s1 += Gd[k] * dbeta[i][k];
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) {
+        s2 += gu[j][k] * d2[BETA + i][j][k];
+        s4 += cdu[i][j][k] * Atu[j][k];
+      }
+    for (int j = 0; j < 3; j++) {
+      double dd = 0.0;
+      for (int k = 0; k < 3; k++) dd += d2[BETA + k][j][k];
+      s3 += gu[i][j] * dd;
+      s5 += Atu[i][j] * dalp[j];
+      s6 += Atu[i][j] * dchi[j];
+      s7 += gu[i][j] * dK[j];
+    }
+    Gnoadv[i] = -s1 + (2.0 / 3.0) * Gd[i] * divbeta + s2 + s3 / 3.0 - 2.0 * s5 +
+                2.0 * alpha * (s4 - 1.5 * s6 / chi - (2.0 / 3.0) * s7);
+    out[GAM + i] = adv[GAM + i] + Gnoadv[i];
+  }
+
+  /* gauge */
+  if (p->slicing == 1)
+    out[ALP] = adv[ALP] - alpha * alpha * trK;
+  else
+    out[ALP] = adv[ALP] - 2.0 * alpha * trK;
+  for (int i = 0; i < 3; i++) {
+    if (p->shift == 1) {
+      out[BETA + i] = adv[BETA + i] + p->shift_F * u[BB + i];
+      out[BB + i] = adv[BB + i] + Gnoadv[i] - p->eta * u[BB + i];
+    } else {
+      out[BETA + i] = 0.0;
+      out[BB + i] = 0.0;
+    }
+  }
+}
+
+void orc_bssn_rhs(const orc_params* p, const double* y, double* r) {
+  geom G = mkgeom(p);
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < G.n[2]; k++)
+    for (int j = 0; j < G.n[1]; j++)
+      for (int i = 0; i < G.n[0]; i++) {
+        const long q = idx(&G, i, j, k);
+        double o[NB];
+        bssn_point(p, &G, y, q, o, NULL);
+        for (int v = 0; v < NB; v++) r[v * G.npts + q] = o[v];
+      }
+}
+
+/* Hamiltonian and momentum constraints; hm (4 grid functions, may be NULL)
+ * receives H, M^1, M^2, M^3 at interior points; norms[c] = sqrt(mean over
+ * interior points of the square), summed plane by plane in a fixed order. */
+void orc_bssn_constraints(const orc_params* p, const double* y, double* hm,
+                          double norms[4]) {
+  geom G = mkgeom(p);
+  const int nz = G.n[2];
+  double* plane = calloc((size_t)nz * 4, sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; k++)
+    for (int j = 0; j < G.n[1]; j++)
+      for (int i = 0; i < G.n[0]; i++) {
+        const long q = idx(&G, i, j, k);
+        double c[4];
+        bssn_point(p, &G, y, q, NULL, c);
+        for (int v = 0; v < 4; v++) {
+          if (hm) hm[v * G.npts + q] = c[v];
+          plane[k * 4 + v] += c[v] * c[v];
+        }
+      }
+  const double npts = (double)G.n[0] * G.n[1] * G.n[2];
+  for (int v = 0; v < 4; v++) {
+    double s = 0.0;
+    for (int k = 0; k < nz; k++) s += plane[k * 4 + v];
+    norms[v] = sqrt(s / npts);
+  }
+  free(plane);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Classical RK4 method of lines (Sec. II: the time-integrator thorn).
+ * Ghosts are refilled before every right-hand-side evaluation, analytic
+ * ghosts at the stage time t_n + c_s dt with c = (0, 1/2, 1/2, 1).        */
+
+static void rhs(const orc_params* p, int system, const double* y, double* r) {
+  if (system == ORC_WAVE)
+    orc_wave_rhs(p, y, r);
+  else
+    orc_bssn_rhs(p, y, r);
+}
+
+/* out = y + c * k on interior points */
+static void axpy_interior(const geom* G, int nvar, const double* y, double c,
+                          const double* k, double* out) {
+  for (int v = 0; v < nvar; v++) {
+    const long o = v * G->npts;
+#pragma omp parallel for schedule(static)
+    for (int kk = 0; kk < G->n[2]; kk++)
+      for (int j = 0; j < G->n[1]; j++)
+        for (int i = 0; i < G->n[0]; i++) {
+          const long q = o + idx(G, i, j, kk);
+          out[q] = y[q] + c * k[q];
+        }
+  }
+}
+
+int orc_rk4(const orc_params* p, int system, int bc, double* y, double t, double dt,
+            int nsteps) {
+  geom G = mkgeom(p);
+  const int nvar = (system == ORC_WAVE) ? 2 : NB;
+  const size_t N = (size_t)nvar * G.npts;
+  double* ys = calloc(N, sizeof(double));
+  double* k1 = calloc(N, sizeof(double));
+  double* k2 = calloc(N, sizeof(double));
+  double* k3 = calloc(N, sizeof(double));
+  double* k4 = calloc(N, sizeof(double));
+  if (!ys || !k1 || !k2 || !k3 || !k4) {
+    free(ys); free(k1); free(k2); free(k3); free(k4);
+    return 1;
+  }
+  memcpy(ys, y, N * sizeof(double));
+  for (int n = 0; n < nsteps; n++) {
+    fill_ghosts(p, system, bc, t, y);
+    rhs(p, system, y, k1);
+    axpy_interior(&G, nvar, y, 0.5 * dt, k1, ys);
+    fill_ghosts(p, system, bc, t + 0.5 * dt, ys);
+    rhs(p, system, ys, k2);
+    axpy_interior(&G, nvar, y, 0.5 * dt, k2, ys);
+    fill_ghosts(p, system, bc, t + 0.5 * dt, ys);
+    rhs(p, system, ys, k3);
+    axpy_interior(&G, nvar, y, dt, k3, ys);
+    fill_ghosts(p, system, bc, t + dt, ys);
+    rhs(p, system, ys, k4);
+    for (int v = 0; v < nvar; v++) {
+      const long o = v * G.npts;
+#pragma omp parallel for schedule(static)
+      for (int kk = 0; kk < G.n[2]; kk++)
+        for (int j = 0; j < G.n[1]; j++)
+          for (int i = 0; i < G.n[0]; i++) {
+            const long q = o + idx(&G, i, j, kk);
+            y[q] = y[q] + (dt / 6.0) * (((k1[q] + 2.0 * k2[q]) + 2.0 * k3[q]) + k4[q]);
+          }
+    }
+    t = t + dt;
+  }
+  fill_ghosts(p, system, bc, t, y);
+  free(ys); free(k1); free(k2); free(k3); free(k4);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* single stencil probe on interior points, for checking the operators on
+ * their own: kind 1 = centred first derivative along a; kind 2 = centred
+ * second derivative d_a d_b (pure when a == b, mixed otherwise); kind 3 =
+ * lopsided derivative along a, upwind side from the sign of sgn (NULL: +). */
+void orc_stencil(const orc_params* p, const double* f, int kind, int a, int b,
+                 const double* sgn, double* out) {
+  geom G = mkgeom(p);
+  const long st[3] = {1, G.sy, G.sz};
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < G.n[2]; k++)
+    for (int j = 0; j < G.n[1]; j++)
+      for (int i = 0; i < G.n[0]; i++) {
+        const long q = idx(&G, i, j, k);
+        double v;
+        if (kind == 1)
+          v = fd1(f + q, st[a], p->h[a]);
+        else if (kind == 2)
+          v = (a == b) ? fd2(f + q, st[a], p->h[a])
+                       : fd11(f + q, st[a], st[b], p->h[a], p->h[b]);
+        else
+          v = fdup(f + q, st[a], p->h[a], sgn ? sgn[q] : 1.0);
+        out[q] = v;
+      }
+}
