@@ -73,35 +73,48 @@ int orc_num_threads(void) { return omp_get_max_threads(); }
 /* 4th-order finite-difference operators (Sec. III.B.2: standard centred
  * operators of a chosen order; the lopsided pair is the 4th-order
  * one-sided-by-one-point stencil used for advection terms).
- * f points at the centre value; s is the stride along the axis.            */
+ * f points at the centre value; s is the stride along the axis.
+ *
+ * Each operator is written on differences of neighbouring values (its
+ * weights sum to zero, so this is the same linear combination).  For data
+ * that is nearly constant -- e.g. flat space plus 1e-10 noise -- such a
+ * difference is exact in floating point, whereas summing the weighted values
+ * themselves would round at the size of the constant and lose the signal.  */
 
 static double fd1(const double* f, long s, double h) {
-  return (f[-2 * s] - 8.0 * f[-s] + 8.0 * f[s] - f[2 * s]) / (12.0 * h);
+  const double d1 = f[s] - f[-s], d2 = f[2 * s] - f[-2 * s];
+  return (8.0 * d1 - d2) / (12.0 * h);
 }
 
 static double fd2(const double* f, long s, double h) {
-  return (-f[-2 * s] + 16.0 * f[-s] - 30.0 * f[0] + 16.0 * f[s] - f[2 * s]) /
-         (12.0 * h * h);
+  const double s1 = (f[s] - f[0]) + (f[-s] - f[0]);
+  const double s2 = (f[2 * s] - f[0]) + (f[-2 * s] - f[0]);
+  return (16.0 * s1 - s2) / (12.0 * h * h);
 }
 
-/* mixed derivative: product of the centred first-derivative stencil along
- * both axes */
+/* mixed derivative: the centred first-derivative stencil applied along both
+ * axes, grouped as q_mn = [f(m,n) - f(-m,n)] - [f(m,-n) - f(-m,-n)] with
+ * weights 8 (offset 1) and -1 (offset 2) along each axis */
 static double fd11(const double* f, long sa, long sb, double ha, double hb) {
-  static const int off[4] = {-2, -1, 1, 2};
-  static const double w[4] = {1.0, -8.0, 8.0, -1.0};
-  double acc = 0.0;
-  for (int a = 0; a < 4; a++)
-    for (int b = 0; b < 4; b++) acc += w[a] * w[b] * f[off[a] * sa + off[b] * sb];
-  return acc / (144.0 * ha * hb);
+  double q[3][3];
+  for (int m = 1; m <= 2; m++)
+    for (int n = 1; n <= 2; n++)
+      q[m][n] = (f[m * sa + n * sb] - f[-m * sa + n * sb]) -
+                (f[m * sa - n * sb] - f[-m * sa - n * sb]);
+  return (64.0 * q[1][1] - 8.0 * q[1][2] - 8.0 * q[2][1] + q[2][2]) / (144.0 * ha * hb);
 }
 
 /* lopsided first derivative, shifted one point towards the upwind side
- * chosen by the sign of the advecting velocity */
+ * chosen by the sign of the advecting velocity: weights (-3, -10, 18, -6, 1)
+ * at offsets (-1, 0, 1, 2, 3) for vel >= 0, mirrored for vel < 0 */
 static double fdup(const double* f, long s, double h, double vel) {
+  const double f0 = f[0];
   if (vel >= 0.0)
-    return (-3.0 * f[-s] - 10.0 * f[0] + 18.0 * f[s] - 6.0 * f[2 * s] + f[3 * s]) /
+    return (-3.0 * (f[-s] - f0) + 18.0 * (f[s] - f0) - 6.0 * (f[2 * s] - f0) +
+            (f[3 * s] - f0)) /
            (12.0 * h);
-  return (3.0 * f[s] + 10.0 * f[0] - 18.0 * f[-s] + 6.0 * f[-2 * s] - f[-3 * s]) /
+  return (3.0 * (f[s] - f0) - 18.0 * (f[-s] - f0) + 6.0 * (f[-2 * s] - f0) -
+          (f[-3 * s] - f0)) /
          (12.0 * h);
 }
 
