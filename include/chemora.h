@@ -1,0 +1,214 @@
+/*
+ * chemora.h -- C ABI of libchemora: MI355X (gfx950) evaluation of the
+ * time-evolution right-hand side of a PDE system on a 3-D uniform grid block
+ * with ghost zones, and the RK4 method of lines built on it.
+ *
+ * The calls follow the paper's statement of the problem (Schnetter et al.,
+ * "Chemora: A PDE Solving Framework for Modern HPC Architectures",
+ * arXiv:1410.1764):
+ *   - a state vector of grid functions plus run-time parameters
+ *     (Sec. III.B.1, "Physics system description"; Fig. 1, the groups
+ *     "Evolved" and "parameters");
+ *   - an RHS calculation, i.e. one loop kernel over the grid (Fig. 1, the
+ *     calculation "RHS"; Sec. III.D, several thousand flops per point for the
+ *     Einstein equations);
+ *   - a driver that owns the grid, its ghost zones and device memory
+ *     (Sec. II, the driver thorn);
+ *   - a separate Runge-Kutta time integrator (Sec. II, the time-integrator
+ *     thorn);
+ *   - many grid patches of a mesh-refinement or multi-block hierarchy
+ *     (Sec. IV, the Carpet driver) advanced together.
+ *
+ * Conventions common to every call
+ * --------------------------------
+ * Memory.  Every array argument named state, rhs, workspace, hm, norms or
+ * meta is DEVICE memory owned by the caller (for example a torch tensor's
+ * data_ptr()).  The library never allocates or frees device memory for
+ * data and never keeps a pointer after a call returns, except the batch
+ * plan (chemora_batch_step), which keeps the pointers of its patch list
+ * until chemora_batch_release.  Grid objects hold host metadata only.
+ *
+ * Layout.  A grid function is stored x fastest with element strides
+ * (1, sy, sz) reported by chemora_grid_layout; point (i, j, k) with each
+ * index in [-ghost, n + ghost) sits at element interior_offset + i + j*sy +
+ * k*sz.  Rows are padded so that interior x = 0 starts on a 128-byte
+ * boundary.  The nvars grid functions of a state follow each other at the
+ * stride sv.  Every value is an IEEE double (FP64) in memory, in both
+ * precision modes.  Variable order:
+ *   wave (2):  u, rho
+ *   BSSN (24): chi, gt11, gt12, gt13, gt22, gt23, gt33, trK, At11, At12,
+ *              At13, At22, At23, At33, Gamt1, Gamt2, Gamt3, alpha, beta1,
+ *              beta2, beta3, B1, B2, B3
+ * Pointers must be 256-byte aligned.
+ *
+ * Streams.  chemora_stream is a hipStream_t (NULL = the null stream).  Every
+ * compute call only enqueues work on that stream and returns; kernel faults
+ * surface at the caller's next synchronisation.
+ *
+ * Errors.  Every call returns a chemora_status.  Argument errors are found
+ * before anything is enqueued; a failed launch returns CHEMORA_ERR_DEVICE.
+ * chemora_last_error() describes the last failure on the calling thread.
+ * Nothing throws or aborts across the ABI.
+ */
+#ifndef CHEMORA_H
+#define CHEMORA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chemora_grid chemora_grid; /* opaque, host-side metadata */
+typedef void* chemora_stream;             /* hipStream_t; NULL = null stream */
+
+typedef enum {
+  CHEMORA_OK = 0,
+  CHEMORA_ERR_INVALID = 1,     /* bad argument; nothing was enqueued */
+  CHEMORA_ERR_UNSUPPORTED = 2, /* valid but not implemented combination */
+  CHEMORA_ERR_DEVICE = 3,      /* HIP runtime or launch failure */
+  CHEMORA_ERR_HOST_NOMEM = 4   /* host allocation failed */
+} chemora_status;
+
+enum { CHEMORA_WAVE = 1, CHEMORA_BSSN = 2 };
+/* FP64: all arithmetic in double.  MIXED: differences of neighbouring
+ * values in double, then stencil weights and the right-hand-side algebra in
+ * float; state, RK4 accumulation and constraints stay double. */
+enum { CHEMORA_FP64 = 0, CHEMORA_MIXED = 1 };
+/* ghost zones: periodic images; the analytic gauge wave at the (stage)
+ * time (BSSN only); or left to the caller (chemora_rhs only). */
+enum { CHEMORA_BC_PERIODIC = 0, CHEMORA_BC_GAUGEWAVE = 1, CHEMORA_BC_CALLER = 2 };
+enum { CHEMORA_SLICING_1PLUSLOG = 0, CHEMORA_SLICING_HARMONIC = 1 };
+enum { CHEMORA_SHIFT_FROZEN = 0, CHEMORA_SHIFT_GAMMADRIVER = 1 };
+
+/* Grid description (Sec. II driver: grid and ghost zones; Sec. III.B.1:
+ * run-time parameters of the physics system). */
+typedef struct {
+  int32_t n[3];      /* interior points per axis, each >= 1 */
+  int32_t ghost;     /* ghost width: >= 2 for the wave, >= 3 for BSSN, <= 8 */
+  double h[3];       /* spacing per axis, > 0 */
+  double origin[3];  /* coordinate of interior point (0,0,0) */
+  int32_t system;    /* CHEMORA_WAVE or CHEMORA_BSSN */
+  int32_t precision; /* CHEMORA_FP64 or CHEMORA_MIXED */
+  int32_t boundary;  /* CHEMORA_BC_*; periodic needs n >= ghost per axis */
+  int32_t slicing;   /* BSSN: 1+log (dt alpha = adv - 2 alpha K) or harmonic (- alpha^2 K) */
+  int32_t shift;     /* BSSN: frozen (dt beta = dt B = 0) or Gamma-driver */
+  double shift_F;    /* Gamma-driver: dt beta^i = adv + F B^i (usually 0.75) */
+  double eta;        /* Gamma-driver damping: dt B^i = ... - eta B^i (usually 2) */
+  double gw_amp;     /* gauge wave amplitude A, |A| < 1 */
+  double gw_wavelength; /* gauge wave wavelength d > 0 */
+  int32_t gw_axis;   /* gauge wave direction 0, 1 or 2 */
+  int32_t reserved;  /* must be 0 */
+} chemora_grid_desc;
+
+/* Create a grid object from a description (copied).  Validates every field
+ * (see chemora_grid_desc) and returns CHEMORA_ERR_INVALID with a message on
+ * the first violation.  *out receives the new object; destroy it with
+ * chemora_grid_destroy. */
+int chemora_grid_create(const chemora_grid_desc* desc, chemora_grid** out);
+int chemora_grid_destroy(chemora_grid* grid);
+
+/* Layout of one state: nvars grid functions; strides[0..3] = element strides
+ * along x, y, z and between variables; interior_offset = element index of
+ * interior point (0,0,0) of variable 0; state_elems = number of doubles a
+ * state array must hold.  Any output pointer may be NULL. */
+int chemora_grid_layout(const chemora_grid* grid, int32_t* nvars, int64_t strides[4],
+                        int64_t* interior_offset, int64_t* state_elems);
+
+/* Bytes of device workspace chemora_rk4_step needs: two stage buffers and
+ * the RK4 accumulator, each a full state.  Returns -1 for a NULL grid. */
+int64_t chemora_workspace_bytes(const chemora_grid* grid);
+
+/* Fill the ghost zones of state (Sec. II: the driver owns ghost zones):
+ * periodic images (x, then y, then z, so edges and corners are filled), or
+ * the analytic gauge wave evaluated at time t (BSSN).  BC_CALLER: nothing to
+ * do, returns CHEMORA_OK. */
+int chemora_fill_ghosts(chemora_grid* grid, double* state, double t, chemora_stream stream);
+
+/* One evaluation of the right-hand side (Fig. 1 "RHS"; eq. (1) for the wave
+ * system, two-variable reading du/dt = rho, drho/dt = Laplacian u; the BSSN
+ * form of the Einstein equations, Sec. III.D) with 4th-order centred
+ * differences and 4th-order lopsided (upwind) differences for the advection
+ * terms.  Reads state at interior points and their stencil neighbours,
+ * i.e. the ghosts must already be valid (chemora_fill_ghosts); writes rhs
+ * (same layout as a state, FP64 in both precision modes) at interior points
+ * only.  state and rhs must not overlap. */
+int chemora_rhs(chemora_grid* grid, const double* state, double* rhs, chemora_stream stream);
+
+/* Advance state by nsteps classical RK4 steps of size dt starting at time t
+ * (Sec. II: the time-integrator thorn).  Ghosts are refilled before every
+ * right-hand-side evaluation -- periodic ghosts are written by the kernel
+ * that produces each stage; analytic ghosts use the stage time
+ * t_n + c_s dt, c = (0, 1/2, 1/2, 1) -- and are valid on return at time
+ * t + nsteps*dt.  workspace: chemora_workspace_bytes(grid) bytes, contents
+ * ignored.  BC_CALLER is rejected (CHEMORA_ERR_INVALID). */
+int chemora_rk4_step(chemora_grid* grid, double* state, void* workspace, double t, double dt,
+                     int32_t nsteps, chemora_stream stream);
+
+/* Hamiltonian and momentum constraints of the BSSN system (Sec. III.B.1:
+ * constraints belong to the physics description), FP64 in both precision
+ * modes, centred stencils only; ghosts must be valid.  hm (may be NULL):
+ * a 4-variable state (H, M1, M2, M3) written at interior points.  norms:
+ * device double[4], the RMS over interior points of H, M1, M2, M3, reduced
+ * in a fixed order (bitwise reproducible).  workspace:
+ * chemora_constraints_workspace_bytes(grid) bytes.  Wave grids:
+ * CHEMORA_ERR_UNSUPPORTED. */
+int64_t chemora_constraints_workspace_bytes(const chemora_grid* grid);
+int chemora_constraints(chemora_grid* grid, const double* state, double* hm, double* norms,
+                        void* workspace, chemora_stream stream);
+
+/* ---- batches of uneven patches (Sec. IV: mesh-refinement / multi-block
+ * patches of the Carpet driver; Sec. III.B.3: a GPU run-time library that
+ * auto-tunes the thread assignment with a performance model) ----------- */
+
+typedef struct {
+  chemora_grid* grid; /* a BSSN grid with boundary CHEMORA_BC_GAUGEWAVE */
+  double* state;      /* its state (device) */
+  void* workspace;    /* chemora_workspace_bytes(grid) bytes (device) */
+} chemora_patch;
+
+/* Device bytes of the plan buffer for a batch of npatches patches (patch
+ * descriptors, work list, device clock).  Returns -1 if npatches < 1. */
+int64_t chemora_batch_meta_bytes(int32_t npatches);
+
+/* Advance every patch by nsteps RK4 steps of size dt from time t.  All
+ * patches must share one system (BSSN), one precision and the gauge-wave
+ * boundary.  Each RK substage is ONE persistent kernel launch over a work
+ * list of (patch, tile) items plus the analytic ghost zones of the next
+ * stage; the four substages and the clock update are captured once in a
+ * HIP graph that is replayed once per step.  The plan (tile shape per
+ * patch, work list, graph) is built on the first call for a given meta
+ * buffer and patch list, and reused while the same meta pointer, patch list
+ * and dt are passed; meta: chemora_batch_meta_bytes(npatches) device bytes
+ * that the caller keeps alive until chemora_batch_release(meta). */
+int chemora_batch_step(const chemora_patch* patches, int32_t npatches, void* meta, double t,
+                       double dt, int32_t nsteps, chemora_stream stream);
+int chemora_batch_release(void* meta);
+
+/* Measure tile shapes for each size class of the given patches with short
+ * timed trials after a model-driven pruning (halo overhead, occupancy,
+ * wave quantisation), and record the winners in an in-process table used
+ * by later batch plans; when table_path is not NULL also write the table
+ * there as JSON.  Runs kernels on the null stream and synchronises. */
+int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
+                     const char* table_path);
+
+/* Tile shape the batch planner would use for a patch of size n (after
+ * chemora_autotune, the tuned one): tile[0..2] in points. */
+int chemora_batch_tile(const int32_t n[3], int32_t precision, int32_t tile[3]);
+
+/* ---- measurement helper --------------------------------------------- */
+
+/* Streaming copy of nbytes (multiple of 16) from src to dst on stream: the
+ * denominator used to calibrate hardware counters and achievable HBM
+ * bandwidth. */
+int chemora_probe_copy(void* dst, const void* src, int64_t nbytes, chemora_stream stream);
+
+/* Thread-local description of the last failure; never NULL. */
+const char* chemora_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEMORA_H */

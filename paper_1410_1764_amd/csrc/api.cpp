@@ -1,0 +1,296 @@
+// api.cpp -- the C ABI of libchemora (declared in include/chemora.h): grid
+// objects, argument validation, the RK4 driver and error reporting.  Host
+// code only; every kernel launch goes through the launchers in internal.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+using namespace chemora;
+
+struct chemora_grid {
+  chemora_grid_desc d;
+  Geo geo;
+  BssnPar par;
+  int nvars;
+  long long state_elems;
+};
+
+namespace chemora {
+
+static thread_local std::string g_err = "no error";
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return status;
+}
+
+int device_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return CHEMORA_OK;
+  return fail(CHEMORA_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+const Geo& grid_geo(const chemora_grid* g) { return g->geo; }
+const BssnPar& grid_par(const chemora_grid* g) { return g->par; }
+const chemora_grid_desc& grid_desc(const chemora_grid* g) { return g->d; }
+long long grid_state_elems(const chemora_grid* g) { return g->state_elems; }
+
+}  // namespace chemora
+
+namespace {
+
+int validate_desc(const chemora_grid_desc* d) {
+  if (!d) return fail(CHEMORA_ERR_INVALID, "grid description is NULL");
+  if (d->system != CHEMORA_WAVE && d->system != CHEMORA_BSSN)
+    return fail(CHEMORA_ERR_INVALID, "system must be CHEMORA_WAVE (1) or CHEMORA_BSSN (2), got %d",
+                d->system);
+  const int gmin = d->system == CHEMORA_WAVE ? 2 : 3;
+  if (d->ghost < gmin || d->ghost > kMaxGhost)
+    return fail(CHEMORA_ERR_INVALID, "ghost must be in [%d, %d] for this system, got %d", gmin,
+                kMaxGhost, d->ghost);
+  for (int a = 0; a < 3; ++a) {
+    if (d->n[a] < 1) return fail(CHEMORA_ERR_INVALID, "n[%d] must be >= 1, got %d", a, d->n[a]);
+    if (!(d->h[a] > 0.0) || !std::isfinite(d->h[a]))
+      return fail(CHEMORA_ERR_INVALID, "h[%d] must be finite and > 0", a);
+    if (!std::isfinite(d->origin[a]))
+      return fail(CHEMORA_ERR_INVALID, "origin[%d] must be finite", a);
+  }
+  if (d->precision != CHEMORA_FP64 && d->precision != CHEMORA_MIXED)
+    return fail(CHEMORA_ERR_INVALID, "precision must be CHEMORA_FP64 or CHEMORA_MIXED, got %d",
+                d->precision);
+  if (d->boundary < CHEMORA_BC_PERIODIC || d->boundary > CHEMORA_BC_CALLER)
+    return fail(CHEMORA_ERR_INVALID, "unknown boundary %d", d->boundary);
+  if (d->boundary == CHEMORA_BC_PERIODIC)
+    for (int a = 0; a < 3; ++a)
+      if (d->n[a] < d->ghost)
+        return fail(CHEMORA_ERR_INVALID,
+                    "periodic boundary needs n[%d] >= ghost (%d < %d): images would overlap",
+                    a, d->n[a], d->ghost);
+  if (d->boundary == CHEMORA_BC_GAUGEWAVE) {
+    if (d->system != CHEMORA_BSSN)
+      return fail(CHEMORA_ERR_INVALID, "the gauge-wave boundary needs the BSSN system");
+    if (!(std::fabs(d->gw_amp) < 1.0))
+      return fail(CHEMORA_ERR_INVALID, "gauge wave amplitude must satisfy |A| < 1");
+    if (!(d->gw_wavelength > 0.0) || !std::isfinite(d->gw_wavelength))
+      return fail(CHEMORA_ERR_INVALID, "gauge wave wavelength must be finite and > 0");
+    if (d->gw_axis < 0 || d->gw_axis > 2)
+      return fail(CHEMORA_ERR_INVALID, "gauge wave axis must be 0, 1 or 2");
+  }
+  if (d->system == CHEMORA_BSSN) {
+    if (d->slicing != CHEMORA_SLICING_1PLUSLOG && d->slicing != CHEMORA_SLICING_HARMONIC)
+      return fail(CHEMORA_ERR_INVALID, "unknown slicing %d", d->slicing);
+    if (d->shift != CHEMORA_SHIFT_FROZEN && d->shift != CHEMORA_SHIFT_GAMMADRIVER)
+      return fail(CHEMORA_ERR_INVALID, "unknown shift condition %d", d->shift);
+    if (!std::isfinite(d->shift_F) || !std::isfinite(d->eta))
+      return fail(CHEMORA_ERR_INVALID, "shift_F and eta must be finite");
+  }
+  if (d->reserved != 0) return fail(CHEMORA_ERR_INVALID, "reserved field must be 0");
+  // element strides of a grid function must fit in 32 bits
+  const long long e0 = d->n[0] + 2LL * d->ghost, e1 = d->n[1] + 2LL * d->ghost;
+  const long long e2 = d->n[2] + 2LL * d->ghost;
+  const long long sy = ((kAlign + d->n[0] + d->ghost + kAlign - 1) / kAlign) * kAlign;
+  if (sy * e1 > (1LL << 30) || sy * e1 * e2 > (1LL << 40) || e0 <= 0)
+    return fail(CHEMORA_ERR_INVALID, "grid too large");
+  return CHEMORA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* chemora_last_error(void) { return g_err.c_str(); }
+
+int chemora_grid_create(const chemora_grid_desc* desc, chemora_grid** out) {
+  if (!out) return fail(CHEMORA_ERR_INVALID, "out pointer is NULL");
+  *out = nullptr;
+  int st = validate_desc(desc);
+  if (st != CHEMORA_OK) return st;
+  chemora_grid* g = new (std::nothrow) chemora_grid;
+  if (!g) return fail(CHEMORA_ERR_HOST_NOMEM, "host allocation failed");
+  g->d = *desc;
+  const int gh = desc->ghost;
+  Geo& G = g->geo;
+  for (int a = 0; a < 3; ++a) G.n[a] = desc->n[a];
+  G.g = gh;
+  // row: [pad | ghost | interior (starts at column kAlign) | ghost | pad]
+  G.sy = (int)(((kAlign + desc->n[0] + gh + kAlign - 1) / kAlign) * kAlign);
+  G.sz = G.sy * (desc->n[1] + 2 * gh);
+  G.sv = (long long)G.sz * (desc->n[2] + 2 * gh);
+  G.off0 = kAlign + (long long)gh * G.sy + (long long)gh * G.sz;
+  g->nvars = desc->system == CHEMORA_WAVE ? 2 : 24;
+  g->state_elems = G.sv * g->nvars;
+  BssnPar& P = g->par;
+  for (int a = 0; a < 3; ++a) {
+    P.h[a] = desc->h[a];
+    P.origin[a] = desc->origin[a];
+  }
+  P.slicing = desc->slicing;
+  P.shift = desc->shift;
+  P.F = desc->shift_F;
+  P.eta = desc->eta;
+  P.gw_A = desc->gw_amp;
+  P.gw_d = desc->gw_wavelength;
+  P.gw_axis = desc->gw_axis;
+  *out = g;
+  return CHEMORA_OK;
+}
+
+int chemora_grid_destroy(chemora_grid* grid) {
+  delete grid;
+  return CHEMORA_OK;
+}
+
+int chemora_grid_layout(const chemora_grid* grid, int32_t* nvars, int64_t strides[4],
+                        int64_t* interior_offset, int64_t* state_elems) {
+  if (!grid) return fail(CHEMORA_ERR_INVALID, "grid is NULL");
+  if (nvars) *nvars = grid->nvars;
+  if (strides) {
+    strides[0] = 1;
+    strides[1] = grid->geo.sy;
+    strides[2] = grid->geo.sz;
+    strides[3] = grid->geo.sv;
+  }
+  if (interior_offset) *interior_offset = grid->geo.off0;
+  if (state_elems) *state_elems = grid->state_elems;
+  return CHEMORA_OK;
+}
+
+int64_t chemora_workspace_bytes(const chemora_grid* grid) {
+  if (!grid) {
+    fail(CHEMORA_ERR_INVALID, "grid is NULL");
+    return -1;
+  }
+  return 3LL * grid->state_elems * (int64_t)sizeof(double);
+}
+
+int chemora_fill_ghosts(chemora_grid* grid, double* state, double t, chemora_stream stream) {
+  if (!grid) return fail(CHEMORA_ERR_INVALID, "grid is NULL");
+  if (!state) return fail(CHEMORA_ERR_INVALID, "state is NULL");
+  if (!aligned(state)) return fail(CHEMORA_ERR_INVALID, "state must be 256-byte aligned");
+  if (!std::isfinite(t)) return fail(CHEMORA_ERR_INVALID, "t must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  switch (grid->d.boundary) {
+    case CHEMORA_BC_PERIODIC:
+      return device_status(launch_fill_periodic(grid->geo, grid->nvars, state, s),
+                           "periodic ghost fill");
+    case CHEMORA_BC_GAUGEWAVE:
+      return device_status(launch_fill_gaugewave(grid->geo, grid->par, t, state, s),
+                           "gauge-wave ghost fill");
+    default:
+      return CHEMORA_OK;
+  }
+}
+
+static hipError_t launch_stage(const chemora_grid* g, int stage, bool images, const StageIO& io,
+                               hipStream_t s) {
+  if (g->d.system == CHEMORA_WAVE)
+    return launch_wave_stage(g->geo, g->d.h, stage, g->d.precision, images, io, s);
+  return launch_bssn_stage(g->geo, g->par, stage, g->d.precision, images, io, s);
+}
+
+int chemora_rhs(chemora_grid* grid, const double* state, double* rhs, chemora_stream stream) {
+  if (!grid) return fail(CHEMORA_ERR_INVALID, "grid is NULL");
+  if (!state || !rhs) return fail(CHEMORA_ERR_INVALID, "state and rhs must not be NULL");
+  if (!aligned(state) || !aligned(rhs))
+    return fail(CHEMORA_ERR_INVALID, "state and rhs must be 256-byte aligned");
+  const long long bytes = grid->state_elems * (long long)sizeof(double);
+  const char* a = reinterpret_cast<const char*>(state);
+  const char* b = reinterpret_cast<const char*>(rhs);
+  if (a < b + bytes && b < a + bytes) return fail(CHEMORA_ERR_INVALID, "state and rhs overlap");
+  StageIO io{state, state, nullptr, rhs, 0.0};
+  return device_status(launch_stage(grid, 0, false, io, static_cast<hipStream_t>(stream)),
+                       "right-hand-side launch");
+}
+
+int chemora_rk4_step(chemora_grid* grid, double* state, void* workspace, double t, double dt,
+                     int32_t nsteps, chemora_stream stream) {
+  if (!grid) return fail(CHEMORA_ERR_INVALID, "grid is NULL");
+  if (!state || !workspace) return fail(CHEMORA_ERR_INVALID, "state and workspace must not be NULL");
+  if (!aligned(state) || !aligned(workspace))
+    return fail(CHEMORA_ERR_INVALID, "state and workspace must be 256-byte aligned");
+  if (nsteps < 0) return fail(CHEMORA_ERR_INVALID, "nsteps must be >= 0");
+  if (!std::isfinite(t) || !std::isfinite(dt)) return fail(CHEMORA_ERR_INVALID, "t and dt must be finite");
+  if (grid->d.boundary == CHEMORA_BC_CALLER)
+    return fail(CHEMORA_ERR_INVALID, "chemora_rk4_step needs a periodic or gauge-wave boundary");
+  const long long E = grid->state_elems;
+  double* B1 = static_cast<double*>(workspace);
+  double* B2 = B1 + E;
+  double* acc = B2 + E;
+  {
+    const char* a = reinterpret_cast<const char*>(state);
+    const char* w = reinterpret_cast<const char*>(workspace);
+    const long long sb = E * 8, wb = 3 * E * 8;
+    if (a < w + wb && w < a + sb) return fail(CHEMORA_ERR_INVALID, "state and workspace overlap");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool periodic = grid->d.boundary == CHEMORA_BC_PERIODIC;
+  int st = chemora_fill_ghosts(grid, state, t, stream);
+  if (st != CHEMORA_OK) return st;
+  const double cdt[5] = {0.0, 0.5 * dt, 0.5 * dt, dt, dt / 6.0};
+  const double ct[5] = {0.0, 0.5, 0.5, 1.0, 1.0};  // time of each stage's output
+  for (int n = 0; n < nsteps; ++n) {
+    const double tn = t + n * dt;
+    double* ins[5] = {nullptr, state, B1, B2, B1};
+    double* outs[5] = {nullptr, B1, B2, B1, state};
+    for (int stage = 1; stage <= 4; ++stage) {
+      StageIO io{ins[stage], state, acc, outs[stage], cdt[stage]};
+      st = device_status(launch_stage(grid, stage, periodic, io, s), "RK4 substage launch");
+      if (st != CHEMORA_OK) return st;
+      if (!periodic) {
+        st = device_status(launch_fill_gaugewave(grid->geo, grid->par, tn + ct[stage] * dt,
+                                                 outs[stage], s),
+                           "gauge-wave ghost fill");
+        if (st != CHEMORA_OK) return st;
+      }
+    }
+  }
+  return CHEMORA_OK;
+}
+
+int64_t chemora_constraints_workspace_bytes(const chemora_grid* grid) {
+  if (!grid) {
+    fail(CHEMORA_ERR_INVALID, "grid is NULL");
+    return -1;
+  }
+  return constraints_partial_count(grid->geo) * (int64_t)sizeof(double);
+}
+
+int chemora_constraints(chemora_grid* grid, const double* state, double* hm, double* norms,
+                        void* workspace, chemora_stream stream) {
+  if (!grid) return fail(CHEMORA_ERR_INVALID, "grid is NULL");
+  if (grid->d.system != CHEMORA_BSSN)
+    return fail(CHEMORA_ERR_UNSUPPORTED, "constraints exist for the BSSN system only");
+  if (!state || !norms || !workspace)
+    return fail(CHEMORA_ERR_INVALID, "state, norms and workspace must not be NULL");
+  if (!aligned(state) || !aligned(workspace) || (hm && !aligned(hm)) ||
+      (reinterpret_cast<uintptr_t>(norms) & 7u))
+    return fail(CHEMORA_ERR_INVALID, "misaligned pointer");
+  return device_status(launch_bssn_constraints(grid->geo, grid->par, state, hm, norms,
+                                               static_cast<double*>(workspace),
+                                               static_cast<hipStream_t>(stream)),
+                       "constraints launch");
+}
+
+int chemora_probe_copy(void* dst, const void* src, int64_t nbytes, chemora_stream stream) {
+  if (!dst || !src) return fail(CHEMORA_ERR_INVALID, "dst and src must not be NULL");
+  if (nbytes < 0 || (nbytes & 15)) return fail(CHEMORA_ERR_INVALID, "nbytes must be a multiple of 16");
+  if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15u)
+    return fail(CHEMORA_ERR_INVALID, "dst and src must be 16-byte aligned");
+  return device_status(launch_probe_copy(dst, src, nbytes, static_cast<hipStream_t>(stream)),
+                       "copy probe launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,495 @@
+// bssn_point.h -- device code for the BSSN right-hand side at one grid point
+// (the Einstein equations evolved in Sec. III.D of arXiv:1410.1764, "several
+// thousand floating point operations ... at a single grid point"), shared by
+// the single-block kernels and the persistent batch kernel.
+//
+// System (chi variant of BSSN; state chi, gt_ij, trK, At_ij, Gamt^i, alpha,
+// beta^i, B^i):
+//   dt chi   = A(chi) + 2/3 chi (alpha K - div beta)
+//   dt gt_ij = A(gt_ij) - 2 alpha At_ij + gt_ik d_j beta^k + gt_jk d_i beta^k
+//              - 2/3 gt_ij div beta
+//   dt K     = A(K) - D^2 alpha + alpha (At^ij At_ij + K^2/3)
+//   dt At_ij = A(At_ij) + chi [-D_i D_j alpha + alpha R_ij]^TF
+//              + alpha (K At_ij - 2 At_ik At^k_j) + At_ik d_j beta^k
+//              + At_jk d_i beta^k - 2/3 At_ij div beta
+//   dt Gt^i  = A(Gt^i) - Gd^k d_k beta^i + 2/3 Gd^i div beta
+//              + gt^jk d_j d_k beta^i + 1/3 gt^ij d_j d_k beta^k
+//              - 2 At^ij d_j alpha
+//              + 2 alpha (Gt^i_jk At^jk - 3/2 At^ij d_j chi / chi - 2/3 gt^ij d_j K)
+//   gauge: dt alpha = A(alpha) - 2 alpha K (1+log) or - alpha^2 K (harmonic);
+//          Gamma-driver dt beta^i = A(beta^i) + F B^i,
+//          dt B^i = A(B^i) + [dt Gt^i - A(Gt^i)] - eta B^i; frozen: 0.
+// A(f) = beta^k d_k f with lopsided (upwind) derivatives; Gd^i = gt^jk Gt^i_jk
+// recomputed from gt (the evolved Gamt^i enters only differentiated and
+// advected); R_ij = conformal Ricci + chi part.
+//
+// Evaluation order is chosen for register pressure ("consume derivatives as
+// they are produced"): the second derivatives of gt_ij are contracted into
+// R_ij right after they are formed, the 18 Christoffels are built from the
+// 18 first derivatives of gt and those are dropped, and so on.  Each
+// variable's stencil values are loaded once and shared by its centred,
+// second and lopsided derivatives.
+//
+// Precision: T is double (FP64) or float (MIXED).  Differences of neighbour
+// values are formed in double, then weighted and combined in T.
+#pragma once
+
+#include "internal.h"
+
+namespace chemora {
+
+enum : int {
+  V_CHI = 0, V_GT = 1, V_TRK = 7, V_AT = 8, V_GAM = 14, V_ALP = 17, V_BETA = 18, V_B = 21,
+  V_N = 24
+};
+
+// index of the symmetric pair (i, j) in (xx, xy, xz, yy, yz, zz); closed
+// form so that it folds to a constant inside unrolled loops
+// Scheduling fences.  Without them the compiler issues the ~700 stencil
+// loads of a point ahead of the arithmetic that consumes them and spills
+// several KB per lane to scratch.  pin() is an empty asm that claims to
+// rewrite x in a VGPR: the value must exist at that point, so the
+// arithmetic producing it cannot sink below the next group's loads, which
+// in turn cannot rise above the memory fence.  No instruction is emitted.
+template <typename T>
+__device__ __forceinline__ void pin(T& x) {
+  asm volatile("" : "+v"(x));
+}
+__device__ __forceinline__ void fence_memory() { asm volatile("" ::: "memory"); }
+
+__host__ __device__ constexpr int sidx(int i, int j) {
+  return (i < j ? i : j) * (5 - (i < j ? i : j)) / 2 + (i < j ? j : i);
+}
+
+// Stencil weights for one block.
+struct Weights {
+  double i12h[3];   // 1 / (12 h_d)
+  double i12hh[3];  // 1 / (12 h_d^2)
+  double i144[3];   // 1 / (144 h_a h_b) for (x,y), (x,z), (y,z)
+};
+
+inline Weights make_weights(const double h[3]) {
+  Weights w;
+  for (int d = 0; d < 3; ++d) {
+    w.i12h[d] = 1.0 / (12.0 * h[d]);
+    w.i12hh[d] = 1.0 / (12.0 * h[d] * h[d]);
+  }
+  w.i144[0] = 1.0 / (144.0 * h[0] * h[1]);
+  w.i144[1] = 1.0 / (144.0 * h[0] * h[2]);
+  w.i144[2] = 1.0 / (144.0 * h[1] * h[2]);
+  return w;
+}
+
+// Centred first derivatives (D1), pure second derivatives (D2) and the
+// advection term beta^k d_k f with the lopsided stencil on the upwind side
+// (ADV) of one grid function; f points at the centre value.
+template <typename T, bool D1, bool D2, bool ADV>
+__device__ __forceinline__ void axis_derivs(const double* __restrict__ f, const long long st[3],
+                                            const Weights& w, const bool bpos[3],
+                                            const T beta[3], T d1[3], T d2[3], T& adv) {
+  const double f0 = f[0];
+  adv = (T)0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const long long s = st[d];
+    const double m1 = f[-s], p1 = f[s], m2 = f[-2 * s], p2 = f[2 * s];
+    if (D1) d1[d] = ((T)8 * (T)(p1 - m1) - (T)(p2 - m2)) * (T)w.i12h[d];
+    if (D2)
+      d2[d] = ((T)16 * (T)((p1 - f0) + (m1 - f0)) - (T)((p2 - f0) + (m2 - f0))) * (T)w.i12hh[d];
+    if (ADV) {
+      const bool up = bpos[d];
+      const double u1 = up ? p1 : m1, um1 = up ? m1 : p1, u2 = up ? p2 : m2;
+      const double u3 = f[up ? 3 * s : -3 * s];
+      T l = ((T)18 * (T)(u1 - f0) - (T)3 * (T)(um1 - f0) - (T)6 * (T)(u2 - f0) + (T)(u3 - f0)) *
+            (T)w.i12h[d];
+      l = up ? l : -l;
+      adv += beta[d] * l;
+    }
+  }
+  if (D1) {
+    pin(d1[0]);
+    pin(d1[1]);
+    pin(d1[2]);
+  }
+  if (D2) {
+    pin(d2[0]);
+    pin(d2[1]);
+    pin(d2[2]);
+  }
+  if (ADV) pin(adv);
+  fence_memory();
+}
+
+// Mixed derivative d_a d_b f: first-derivative stencil along both axes,
+// q_mn = [f(m,n) - f(-m,n)] - [f(m,-n) - f(-m,-n)], weights 8 / -1.
+template <typename T>
+__device__ __forceinline__ T mixed_deriv(const double* __restrict__ f, long long sa, long long sb,
+                                         double wab) {
+  double q[2][2];
+#pragma unroll
+  for (int m = 1; m <= 2; ++m)
+#pragma unroll
+    for (int n = 1; n <= 2; ++n)
+      q[m - 1][n - 1] =
+          (f[m * sa + n * sb] - f[-m * sa + n * sb]) - (f[m * sa - n * sb] - f[-m * sa - n * sb]);
+  return ((T)64 * (T)q[0][0] - (T)8 * (T)q[0][1] - (T)8 * (T)q[1][0] + (T)q[1][1]) * (T)wab;
+}
+
+// All six second derivatives d_a d_b f in symmetric order.
+template <typename T>
+__device__ __forceinline__ void second_derivs(const double* __restrict__ f, const long long st[3],
+                                              const Weights& w, const T d2pure[3], T dd[6]) {
+  dd[0] = d2pure[0];
+  dd[3] = d2pure[1];
+  dd[5] = d2pure[2];
+  dd[1] = mixed_deriv<T>(f, st[0], st[1], w.i144[0]);
+  dd[2] = mixed_deriv<T>(f, st[0], st[2], w.i144[1]);
+  dd[4] = mixed_deriv<T>(f, st[1], st[2], w.i144[2]);
+  pin(dd[1]);
+  pin(dd[2]);
+  pin(dd[4]);
+  fence_memory();
+}
+
+// Geometry shared by the right-hand side and the constraints: inverse
+// conformal metric gu, Christoffels cdu (Gt^i_jk) and their contraction Gd,
+// d_i chi, and the Ricci tensor R_ij (conformal part + chi part).  With ADV
+// the advection terms of gt_ij, Gamt^i and chi are written to rhs as well.
+template <typename T, bool ADV>
+__device__ __forceinline__ void bssn_geometry(const double* __restrict__ Y, long long sv,
+                                              const long long st[3], const Weights& w,
+                                              const bool bpos[3], const T beta[3], T chi,
+                                              const T gt[6], T gu[6], T cdu[3][6], T Gd[3],
+                                              T dchi[3], T R[6], T rhs[V_N]) {
+  auto F = [&](int v) { return Y + v * sv; };
+
+  // ---- inverse conformal metric (adjugate / determinant)
+  {
+    const T c00 = gt[3] * gt[5] - gt[4] * gt[4];
+    const T c01 = gt[2] * gt[4] - gt[1] * gt[5];
+    const T c02 = gt[1] * gt[4] - gt[2] * gt[3];
+    const T c11 = gt[0] * gt[5] - gt[2] * gt[2];
+    const T c12 = gt[1] * gt[2] - gt[0] * gt[4];
+    const T c22 = gt[0] * gt[3] - gt[1] * gt[1];
+    const T idet = (T)1 / (gt[0] * c00 + gt[1] * c01 + gt[2] * c02);
+    gu[0] = c00 * idet;
+    gu[1] = c01 * idet;
+    gu[2] = c02 * idet;
+    gu[3] = c11 * idet;
+    gu[4] = c12 * idet;
+    gu[5] = c22 * idet;
+  }
+
+  T dd[6], dpure[3], adv;
+  T dgt[6][3];
+
+  // ---- gt_ij: first derivatives kept; second derivatives contracted into
+  // R_ij = -1/2 gt^lm d_l d_m gt_ij right away; advection
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const double* f = F(V_GT + q);
+    axis_derivs<T, true, true, ADV>(f, st, w, bpos, beta, dgt[q], dpure, adv);
+    if (ADV) rhs[V_GT + q] = adv;
+    second_derivs<T>(f, st, w, dpure, dd);
+    R[q] = (T)(-0.5) * (gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
+                        (T)2 * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]));
+  }
+
+  // ---- Christoffels of the conformal metric
+  // cdl[i][jk] = 1/2 (d_j gt_ik + d_k gt_ij - d_i gt_jk); cdu = gt^il cdl[l]
+  T cdl[3][6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = j; k < 3; ++k)
+        cdl[i][sidx(j, k)] =
+            (T)0.5 * (dgt[sidx(i, k)][j] + dgt[sidx(i, j)][k] - dgt[sidx(j, k)][i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      cdu[i][q] = gu[sidx(i, 0)] * cdl[0][q] + gu[sidx(i, 1)] * cdl[1][q] +
+                  gu[sidx(i, 2)] * cdl[2][q];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    Gd[i] = gu[0] * cdu[i][0] + gu[3] * cdu[i][3] + gu[5] * cdu[i][5] +
+            (T)2 * (gu[1] * cdu[i][1] + gu[2] * cdu[i][2] + gu[4] * cdu[i][4]);
+
+  // ---- evolved Gamt^i: R_ij += 1/2 (gt_ki d_j Gt^k + gt_kj d_i Gt^k); advection
+  {
+    T dG[3][3];  // dG[k][j] = d_j Gt^k
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      axis_derivs<T, true, false, ADV>(F(V_GAM + k), st, w, bpos, beta, dG[k], dpure, adv);
+      if (ADV) rhs[V_GAM + k] = adv;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) {
+        T s = (T)0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s += gt[sidx(k, i)] * dG[k][j] + gt[sidx(k, j)] * dG[k][i];
+        R[sidx(i, j)] += (T)0.5 * s;
+      }
+  }
+
+  // ---- Christoffel products:
+  // R_ij += 1/2 Gd^k (cdl_ijk + cdl_jik)
+  //       + gt^lm (cdu^k_li cdl_jkm + cdu^k_lj cdl_ikm + cdu^k_im cdl_klj)
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      T s = (T)0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s += Gd[k] * (cdl[i][sidx(j, k)] + cdl[j][sidx(i, k)]);
+      T t = (T)0;
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          T u = (T)0;
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            u += cdu[k][sidx(l, i)] * cdl[j][sidx(k, m)] + cdu[k][sidx(l, j)] * cdl[i][sidx(k, m)] +
+                 cdu[k][sidx(i, m)] * cdl[k][sidx(l, j)];
+          t += gu[sidx(l, m)] * u;
+        }
+      R[sidx(i, j)] += (T)0.5 * s + t;
+    }
+
+  // ---- chi: D_i D_j chi = d_i d_j chi - Gt^k_ij d_k chi; chi part of R_ij
+  {
+    axis_derivs<T, true, true, ADV>(F(V_CHI), st, w, bpos, beta, dchi, dpure, adv);
+    if (ADV) rhs[V_CHI] = adv;
+    second_derivs<T>(F(V_CHI), st, w, dpure, dd);
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      dd[q] -= cdu[0][q] * dchi[0] + cdu[1][q] * dchi[1] + cdu[2][q] * dchi[2];
+    T trDD = gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
+             (T)2 * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]);
+    T dchi2 = (T)0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) dchi2 += gu[sidx(l, m)] * dchi[l] * dchi[m];
+    const T i2chi = (T)0.5 / chi;
+    const T i4chi2 = (T)0.25 / (chi * chi);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) {
+        const int q = sidx(i, j);
+        R[q] += (dd[q] + gt[q] * trDD) * i2chi - (dchi[i] * dchi[j] + (T)3 * gt[q] * dchi2) * i4chi2;
+      }
+  }
+}
+
+// Right-hand side of all 24 variables at one point.  Y points at the centre
+// value of variable 0; variables are sv apart.
+template <typename T>
+__device__ __forceinline__ void bssn_rhs_point(const double* __restrict__ Y, long long sv,
+                                               const long long st[3], const Weights& w,
+                                               const BssnPar& P, T rhs[V_N]) {
+  auto F = [&](int v) { return Y + v * sv; };
+
+  // ---- centre values, upwind sides
+  bool bpos[3];
+  T beta[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double b = F(V_BETA + d)[0];
+    bpos[d] = b >= 0.0;
+    beta[d] = (T)b;
+  }
+  const T chi = (T)F(V_CHI)[0];
+  const T trK = (T)F(V_TRK)[0];
+  const T alpha = (T)F(V_ALP)[0];
+  T gt[6], At[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    gt[q] = (T)F(V_GT + q)[0];
+    At[q] = (T)F(V_AT + q)[0];
+  }
+
+  T gu[6], cdu[3][6], Gd[3], dchi[3], R[6];
+  bssn_geometry<T, true>(Y, sv, st, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, rhs);
+  T dd[6], dpure[3], d1v[3], adv;
+
+  // ---- lapse: D_i D_j alpha with the physical Christoffels
+  // Gamma^k_ij = Gt^k_ij - (delta^k_i d_j chi + delta^k_j d_i chi - gt_ij gt^kl d_l chi) / (2 chi)
+  T dalp[3];
+  T lapalp;
+  T X[6];
+  {
+    axis_derivs<T, true, true, true>(F(V_ALP), st, w, bpos, beta, dalp, dpure, adv);
+    rhs[V_ALP] = adv;
+    second_derivs<T>(F(V_ALP), st, w, dpure, dd);
+    const T i2chi = (T)0.5 / chi;
+    T uchi[3];  // gt^kl d_l chi
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      uchi[k] = gu[sidx(k, 0)] * dchi[0] + gu[sidx(k, 1)] * dchi[1] + gu[sidx(k, 2)] * dchi[2];
+    const T ua = uchi[0] * dalp[0] + uchi[1] * dalp[1] + uchi[2] * dalp[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) {
+        const int q = sidx(i, j);
+        T G = cdu[0][q] * dalp[0] + cdu[1][q] * dalp[1] + cdu[2][q] * dalp[2];
+        G -= (dchi[j] * dalp[i] + dchi[i] * dalp[j] - gt[q] * ua) * i2chi;
+        dd[q] -= G;  // D_i D_j alpha
+      }
+    lapalp = chi * (gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
+                    (T)2 * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]));
+#pragma unroll
+    for (int q = 0; q < 6; ++q) X[q] = alpha * R[q] - dd[q];
+  }
+
+  // ---- At with indices raised by gt^ij
+  T Atm[3][3];  // At^i_j
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Atm[i][j] = gu[sidx(i, 0)] * At[sidx(0, j)] + gu[sidx(i, 1)] * At[sidx(1, j)] +
+                  gu[sidx(i, 2)] * At[sidx(2, j)];
+  T Atu[6];  // At^ij
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j)
+      Atu[sidx(i, j)] = Atm[i][0] * gu[sidx(0, j)] + Atm[i][1] * gu[sidx(1, j)] +
+                        Atm[i][2] * gu[sidx(2, j)];
+  T AtAt = (T)0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) AtAt += Atm[i][j] * Atm[j][i];
+
+  // ---- shift derivatives: d_j beta^k, gt^jk d_j d_k beta^i, d_j d_k beta^k
+  T dbeta[3][3];  // dbeta[k][j] = d_j beta^k
+  T lapb[3], gdiv[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double* f = F(V_BETA + k);
+    axis_derivs<T, true, true, true>(f, st, w, bpos, beta, dbeta[k], dpure, adv);
+    rhs[V_BETA + k] = adv;
+    second_derivs<T>(f, st, w, dpure, dd);
+    lapb[k] = gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
+              (T)2 * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]);
+    // gdiv[j] += d_j d_k beta^k (k fixed here)
+    if (k == 0) {
+      gdiv[0] = dd[sidx(0, 0)];
+      gdiv[1] = dd[sidx(1, 0)];
+      gdiv[2] = dd[sidx(2, 0)];
+    } else {
+      gdiv[0] += dd[sidx(0, k)];
+      gdiv[1] += dd[sidx(1, k)];
+      gdiv[2] += dd[sidx(2, k)];
+    }
+  }
+  const T divb = dbeta[0][0] + dbeta[1][1] + dbeta[2][2];
+
+  // ---- trK (first derivatives + advection), At and B (advection only)
+  T dK[3];
+  axis_derivs<T, true, false, true>(F(V_TRK), st, w, bpos, beta, dK, dpure, adv);
+  rhs[V_TRK] = adv;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    axis_derivs<T, false, false, true>(F(V_AT + q), st, w, bpos, beta, d1v, dpure, adv);
+    rhs[V_AT + q] = adv;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    axis_derivs<T, false, false, true>(F(V_B + q), st, w, bpos, beta, d1v, dpure, adv);
+    rhs[V_B + q] = adv;
+  }
+
+  // ---- assemble
+  const T two3 = (T)2 / (T)3, third = (T)1 / (T)3;
+  rhs[V_CHI] += two3 * chi * (alpha * trK - divb);
+  rhs[V_TRK] += -lapalp + alpha * (AtAt + trK * trK * third);
+
+  T trX = gu[0] * X[0] + gu[3] * X[3] + gu[5] * X[5] +
+          (T)2 * (gu[1] * X[1] + gu[2] * X[2] + gu[4] * X[4]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const int q = sidx(i, j);
+      T sg = (T)0, sa = (T)0, aa = (T)0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        sg += gt[sidx(i, k)] * dbeta[k][j] + gt[sidx(j, k)] * dbeta[k][i];
+        sa += At[sidx(i, k)] * dbeta[k][j] + At[sidx(j, k)] * dbeta[k][i];
+        aa += At[sidx(i, k)] * Atm[k][j];
+      }
+      rhs[V_GT + q] += sg - (T)2 * alpha * At[q] - two3 * gt[q] * divb;
+      rhs[V_AT + q] += chi * (X[q] - gt[q] * trX * third) + alpha * (trK * At[q] - (T)2 * aa) +
+                       sa - two3 * At[q] * divb;
+    }
+
+  const T ichi = (T)1 / chi;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T s = -(Gd[0] * dbeta[i][0] + Gd[1] * dbeta[i][1] + Gd[2] * dbeta[i][2]) + two3 * Gd[i] * divb +
+          lapb[i] +
+          third * (gu[sidx(i, 0)] * gdiv[0] + gu[sidx(i, 1)] * gdiv[1] + gu[sidx(i, 2)] * gdiv[2]);
+    T aal = (T)0, ach = (T)0, gk = (T)0, cA = (T)0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      aal += Atu[sidx(i, j)] * dalp[j];
+      ach += Atu[sidx(i, j)] * dchi[j];
+      gk += gu[sidx(i, j)] * dK[j];
+    }
+    cA = cdu[i][0] * Atu[0] + cdu[i][3] * Atu[3] + cdu[i][5] * Atu[5] +
+         (T)2 * (cdu[i][1] * Atu[1] + cdu[i][2] * Atu[2] + cdu[i][4] * Atu[4]);
+    s += (T)(-2) * aal + (T)2 * alpha * (cA - (T)1.5 * ach * ichi - two3 * gk);
+    rhs[V_GAM + i] += s;
+    if (P.shift == 1) {
+      rhs[V_BETA + i] += (T)P.F * (T)F(V_B + i)[0];
+      rhs[V_B + i] += s - (T)P.eta * (T)F(V_B + i)[0];
+    } else {
+      rhs[V_BETA + i] = (T)0;
+      rhs[V_B + i] = (T)0;
+    }
+  }
+  if (P.slicing == 1)
+    rhs[V_ALP] -= alpha * alpha * trK;
+  else
+    rhs[V_ALP] -= (T)2 * alpha * trK;
+}
+
+// RK4 substage update of one point (see StageIO) from the right-hand side.
+template <int STAGE, typename T>
+__device__ __forceinline__ void bssn_store(const StageIO& io, const Geo& G, long long p, int i,
+                                           int j, int k, const T rhs[V_N], bool images) {
+  double* out = io.out + G.off0;
+#pragma unroll
+  for (int v = 0; v < V_N; ++v) {
+    const long long q = p + v * G.sv;
+    const double kv = (double)rhs[v];
+    if (STAGE == 0) {
+      out[q] = kv;
+      continue;
+    }
+    const double y0 = io.y0[G.off0 + q];
+    double nv;
+    if (STAGE == 1) {
+      io.acc[G.off0 + q] = kv;
+      nv = y0 + io.cdt * kv;
+    } else if (STAGE == 2 || STAGE == 3) {
+      io.acc[G.off0 + q] = io.acc[G.off0 + q] + 2.0 * kv;
+      nv = y0 + io.cdt * kv;
+    } else {
+      nv = y0 + io.cdt * (io.acc[G.off0 + q] + kv);
+    }
+    store_with_images(out + v * G.sv, G, i, j, k, nv, images);
+  }
+}
+
+}  // namespace chemora

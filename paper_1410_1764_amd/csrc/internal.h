@@ -1,0 +1,96 @@
+// internal.h -- shared definitions of libchemora's HIP sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "chemora.h"
+
+namespace chemora {
+
+constexpr int kAlign = 16;  // interior x = 0 starts on a 16-double (128 B) boundary
+constexpr int kMaxGhost = 8;
+constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+
+// Device view of one block's geometry (element strides, x fastest).
+struct Geo {
+  int n[3];
+  int g;
+  int sy, sz;      // strides of y and z within one grid function
+  long long sv;    // stride between grid functions
+  long long off0;  // element index of interior point (0,0,0) of variable 0
+};
+
+// Run-time parameters of the BSSN system and its analytic boundary.
+struct BssnPar {
+  double h[3];
+  double origin[3];
+  int slicing;  // 0: 1+log, 1: harmonic
+  int shift;    // 0: frozen, 1: Gamma-driver
+  double F, eta;
+  double gw_A, gw_d;
+  int gw_axis;
+};
+
+// The four classical RK4 substages fused with the right-hand side.  Stage 0
+// means "right-hand side only".  With k_s the right-hand side of stage s:
+//   s1: acc = k1;            out = y0 + dt/2 k1
+//   s2: acc = acc + 2 k2;    out = y0 + dt/2 k2
+//   s3: acc = acc + 2 k3;    out = y0 + dt k3
+//   s4:                      out = y0 + dt/6 (acc + k4)   (out == y0)
+struct StageIO {
+  const double* yin;  // stencil source (valid ghosts)
+  const double* y0;   // y_n (pointwise)
+  double* acc;        // accumulator (pointwise)
+  double* out;        // stage output, or the rhs for stage 0
+  double cdt;         // dt/2, dt/2, dt, dt/6 for stages 1..4
+};
+
+// Hardware places workgroup b on XCD b % 8.  Give each XCD a contiguous range
+// of tiles so that halo re-reads of neighbouring tiles hit the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb / kNumXcd, r = nb % kNumXcd;
+  const int x = b % kNumXcd, l = b / kNumXcd;
+  return x * q + (x < r ? x : r) + l;
+}
+
+// Periodic write-through: store v at interior point (i,j,k) of one grid
+// function and at every periodic image of it that lies in the ghost zones.
+__device__ __forceinline__ void store_with_images(double* f, const Geo& G, int i, int j, int k,
+                                                  double v, bool images) {
+  f[i + (long long)j * G.sy + (long long)k * G.sz] = v;
+  if (!images) return;
+  int ii[3], jj[3], kk[3];
+  int ci = 1, cj = 1, ck = 1;
+  ii[0] = i;
+  jj[0] = j;
+  kk[0] = k;
+  if (i < G.g) ii[ci++] = i + G.n[0];
+  if (i >= G.n[0] - G.g) ii[ci++] = i - G.n[0];
+  if (j < G.g) jj[cj++] = j + G.n[1];
+  if (j >= G.n[1] - G.g) jj[cj++] = j - G.n[1];
+  if (k < G.g) kk[ck++] = k + G.n[2];
+  if (k >= G.n[2] - G.g) kk[ck++] = k - G.n[2];
+  if (ci == 1 && cj == 1 && ck == 1) return;
+  for (int c = 0; c < ck; ++c)
+    for (int b = 0; b < cj; ++b)
+      for (int a = 0; a < ci; ++a)
+        if (a | b | c) f[ii[a] + (long long)jj[b] * G.sy + (long long)kk[c] * G.sz] = v;
+}
+
+// ---- launchers (host) -----------------------------------------------------
+hipError_t launch_fill_periodic(const Geo& G, int nvar, double* state, hipStream_t s);
+hipError_t launch_fill_gaugewave(const Geo& G, const BssnPar& P, double t, double* state,
+                                 hipStream_t s);
+hipError_t launch_wave_stage(const Geo& G, const double h[3], int stage, int precision,
+                             bool images, const StageIO& io, hipStream_t s);
+hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int precision,
+                             bool images, const StageIO& io, hipStream_t s);
+hipError_t launch_bssn_constraints(const Geo& G, const BssnPar& P, const double* y,
+                                   double* hm, double* norms, double* partial,
+                                   hipStream_t s);
+long long constraints_partial_count(const Geo& G);
+hipError_t launch_probe_copy(void* dst, const void* src, long long nbytes, hipStream_t s);
+
+}  // namespace chemora

@@ -1,0 +1,161 @@
+// wave.hip -- scalar wave right-hand side, eq. (1) of arXiv:1410.1764 in its
+// two-variable reading (du/dt = rho, drho/dt = Laplacian u), with 4th-order
+// centred differences (Sec. III.B.2), alone or fused with an RK4 substage.
+//
+// Memory-bound design (HBM roofline): one workgroup = a 64 x 4 xy tile, one
+// wavefront per x row of 64 contiguous doubles (coalesced), marching along z.
+// u along z lives in a 5-deep register queue; the current xy plane of u goes
+// through LDS with a 2-point halo.  Each value of u is read from memory once
+// per plane by one thread (its centre) plus the halo ring.
+//
+// Precision: the 2nd-derivative stencil is written on neighbour differences,
+// s_a = (f(+a) - f(0)) + (f(-a) - f(0)) (a = 1, 2), d2f = (16 s_1 - s_2) / (12 h^2).
+// The differences are always formed in double; the weights and the sum are
+// done in T (double, or float for the mixed path).  The stage update is
+// always double.
+#include "internal.h"
+
+namespace chemora {
+namespace {
+
+constexpr int TX = 64, TY = 4, R = 2;
+
+struct WaveArgs {
+  Geo G;
+  StageIO io;
+  double w2[3];  // 1 / (12 h^2)
+  int zc;        // z-planes per workgroup
+  int tiles[3];  // workgroups along x, y, z
+  int images;    // write periodic images of the stage output
+};
+
+template <int STAGE, typename T>
+__global__ void __launch_bounds__(TX * TY) wave_stage_kernel(WaveArgs a) {
+  __shared__ double tile[TY + 2 * R][TX + 2 * R];
+  const Geo& G = a.G;
+  const int nb = a.tiles[0] * a.tiles[1] * a.tiles[2];
+  const int b = xcd_tile(blockIdx.x, nb);
+  const int bx = b % a.tiles[0], by = (b / a.tiles[0]) % a.tiles[1], bz = b / (a.tiles[0] * a.tiles[1]);
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int i = bx * TX + tx, j = by * TY + ty;
+  const int k0 = bz * a.zc;
+  const int k1 = min(k0 + a.zc, G.n[2]);
+  const bool comp = i < G.n[0] && j < G.n[1];
+  const bool col_ok = i < G.n[0] + R && j < G.n[1] + R;
+  const double* U = a.io.yin + G.off0;
+  const double* RH = U + G.sv;
+  const long long col = i + (long long)j * G.sy;
+  const long long sz = G.sz;
+
+  double q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0;  // u at k-2 .. k+2
+  if (col_ok) {
+    q0 = U[col + (k0 - 2) * sz];
+    q1 = U[col + (k0 - 1) * sz];
+    q2 = U[col + k0 * sz];
+    q3 = U[col + (k0 + 1) * sz];
+  }
+  const T w2x = (T)a.w2[0], w2y = (T)a.w2[1], w2z = (T)a.w2[2];
+
+  for (int k = k0; k < k1; ++k) {
+    const long long pk = col + k * sz;
+    if (col_ok) q4 = U[pk + 2 * sz];
+    __syncthreads();
+    tile[ty + R][tx + R] = q2;
+    if (tx < R && j < G.n[1] + R) tile[ty + R][tx] = U[pk - R];
+    if (tx >= TX - R && i < G.n[0] && j < G.n[1] + R) tile[ty + R][tx + 2 * R] = U[pk + R];
+    if (ty < R && i < G.n[0] + R) tile[ty][tx + R] = U[pk - (long long)R * G.sy];
+    if (ty >= TY - R && j < G.n[1] && i < G.n[0] + R)
+      tile[ty + 2 * R][tx + R] = U[pk + (long long)R * G.sy];
+    __syncthreads();
+    if (comp) {
+      const double c = q2;
+      const double sx1 = (tile[ty + R][tx + R + 1] - c) + (tile[ty + R][tx + R - 1] - c);
+      const double sx2 = (tile[ty + R][tx + R + 2] - c) + (tile[ty + R][tx + R - 2] - c);
+      const double sy1 = (tile[ty + R + 1][tx + R] - c) + (tile[ty + R - 1][tx + R] - c);
+      const double sy2 = (tile[ty + R + 2][tx + R] - c) + (tile[ty + R - 2][tx + R] - c);
+      const double sz1 = (q3 - c) + (q1 - c);
+      const double sz2 = (q4 - c) + (q0 - c);
+      const T lap = ((T)16 * (T)sx1 - (T)sx2) * w2x + ((T)16 * (T)sy1 - (T)sy2) * w2y +
+                    ((T)16 * (T)sz1 - (T)sz2) * w2z;
+      const double rho = RH[pk];
+      const double ku = rho, kr = (double)lap;
+      const long long p = pk;
+      double* out = a.io.out + G.off0;
+      if (STAGE == 0) {
+        out[p] = ku;
+        out[p + G.sv] = kr;
+      } else {
+        double* acc = a.io.acc + G.off0;
+        const double* y0 = a.io.y0 + G.off0;
+        double u0, r0;
+        if (STAGE == 1) {
+          u0 = c;
+          r0 = rho;
+        } else {
+          u0 = y0[p];
+          r0 = y0[p + G.sv];
+        }
+        double nu, nr;
+        if (STAGE == 1) {
+          acc[p] = ku;
+          acc[p + G.sv] = kr;
+          nu = u0 + a.io.cdt * ku;
+          nr = r0 + a.io.cdt * kr;
+        } else if (STAGE == 2 || STAGE == 3) {
+          acc[p] = acc[p] + 2.0 * ku;
+          acc[p + G.sv] = acc[p + G.sv] + 2.0 * kr;
+          nu = u0 + a.io.cdt * ku;
+          nr = r0 + a.io.cdt * kr;
+        } else {
+          nu = u0 + a.io.cdt * (acc[p] + ku);
+          nr = r0 + a.io.cdt * (acc[p + G.sv] + kr);
+        }
+        store_with_images(out, G, i, j, k, nu, a.images);
+        store_with_images(out + G.sv, G, i, j, k, nr, a.images);
+      }
+    }
+    q0 = q1;
+    q1 = q2;
+    q2 = q3;
+    q3 = q4;
+  }
+}
+
+template <typename T>
+hipError_t launch_t(int stage, const WaveArgs& a, dim3 grid, hipStream_t s) {
+  const dim3 block(TX * TY);
+  switch (stage) {
+    case 0: hipLaunchKernelGGL((wave_stage_kernel<0, T>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((wave_stage_kernel<1, T>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((wave_stage_kernel<2, T>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((wave_stage_kernel<3, T>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((wave_stage_kernel<4, T>), grid, block, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_wave_stage(const Geo& G, const double h[3], int stage, int precision,
+                             bool images, const StageIO& io, hipStream_t s) {
+  WaveArgs a;
+  a.G = G;
+  a.io = io;
+  for (int d = 0; d < 3; ++d) a.w2[d] = 1.0 / (12.0 * h[d] * h[d]);
+  a.images = images ? 1 : 0;
+  a.tiles[0] = (G.n[0] + TX - 1) / TX;
+  a.tiles[1] = (G.n[1] + TY - 1) / TY;
+  // enough workgroups to fill 256 CUs several times over; each marches zc planes
+  const long long xy = (long long)a.tiles[0] * a.tiles[1];
+  const long long want = 4096;
+  int zsplit = (int)((want + xy - 1) / xy);
+  if (zsplit > G.n[2]) zsplit = G.n[2];
+  if (zsplit < 1) zsplit = 1;
+  a.zc = (G.n[2] + zsplit - 1) / zsplit;
+  a.tiles[2] = (G.n[2] + a.zc - 1) / a.zc;
+  const dim3 grid((unsigned)(a.tiles[0] * a.tiles[1] * a.tiles[2]));
+  return precision == CHEMORA_MIXED ? launch_t<float>(stage, a, grid, s)
+                                    : launch_t<double>(stage, a, grid, s);
+}
+
+}  // namespace chemora

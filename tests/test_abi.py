@@ -1,0 +1,108 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/chemora.h declares, and rejects bad arguments with the documented
+status before touching the device."""
+import ctypes
+
+import pytest
+
+from paper_1410_1764_amd import chemora as C
+
+
+def test_library_exports_every_declared_function():
+    L = C.lib()
+    names = C.header_functions()
+    assert len(names) >= 16
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _create(**kw):
+    base = dict(n=(8, 8, 8), ghost=3, h=0.1, system=C.BSSN)
+    base.update(kw)
+    return C.Grid(**base)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n=(0, 8, 8)), "n[0]"),
+    (dict(ghost=2), "ghost"),
+    (dict(system=C.WAVE, ghost=1), "ghost"),
+    (dict(ghost=9), "ghost"),
+    (dict(h=(0.1, 0.0, 0.1)), "h[1]"),
+    (dict(h=(0.1, 0.1, float("nan"))), "h[2]"),
+    (dict(system=3), "system"),
+    (dict(precision=2), "precision"),
+    (dict(boundary=7), "boundary"),
+    (dict(n=(8, 2, 8)), "periodic"),
+    (dict(system=C.WAVE, ghost=2, boundary=C.BC_GAUGEWAVE), "BSSN"),
+    (dict(boundary=C.BC_GAUGEWAVE, gw_amp=1.5), "amplitude"),
+    (dict(boundary=C.BC_GAUGEWAVE, gw_axis=3), "axis"),
+    (dict(boundary=C.BC_GAUGEWAVE, gw_wavelength=0.0), "wavelength"),
+    (dict(slicing=5), "slicing"),
+    (dict(shift=5), "shift"),
+    (dict(reserved=1), "reserved"),
+])
+def test_grid_create_rejects(kw, msg):
+    with pytest.raises(C.ChemoraError) as e:
+        _create(**kw)
+    assert e.value.status == C.ERR_INVALID
+    assert msg in str(e.value)
+
+
+def test_null_arguments():
+    L = C.lib()
+    assert L.chemora_grid_create(None, None) == C.ERR_INVALID
+    h = ctypes.c_void_p()
+    assert L.chemora_grid_create(None, ctypes.byref(h)) == C.ERR_INVALID
+    assert "NULL" in C.last_error()
+    assert L.chemora_workspace_bytes(None) == -1
+    assert L.chemora_rhs(None, None, None, None) == C.ERR_INVALID
+    g = _create()
+    assert L.chemora_rhs(g.handle, None, None, None) == C.ERR_INVALID
+    assert L.chemora_rk4_step(g.handle, None, None, 0.0, 0.1, 1, None) == C.ERR_INVALID
+    # misaligned pointers are rejected before any launch
+    assert L.chemora_rhs(g.handle, ctypes.c_void_p(8), ctypes.c_void_p(4096), None) == C.ERR_INVALID
+    assert "aligned" in C.last_error()
+    # overlapping state / rhs
+    assert L.chemora_rhs(g.handle, ctypes.c_void_p(4096), ctypes.c_void_p(4096), None) == C.ERR_INVALID
+    assert "overlap" in C.last_error()
+    assert L.chemora_rk4_step(g.handle, ctypes.c_void_p(4096), ctypes.c_void_p(1 << 40), 0.0,
+                              0.1, -1, None) == C.ERR_INVALID
+    assert L.chemora_rk4_step(g.handle, ctypes.c_void_p(4096), ctypes.c_void_p(1 << 40), 0.0,
+                              float("inf"), 1, None) == C.ERR_INVALID
+
+
+def test_caller_boundary_rejected_by_rk4():
+    g = _create(boundary=C.BC_CALLER)
+    assert C.lib().chemora_rk4_step(g.handle, ctypes.c_void_p(4096), ctypes.c_void_p(1 << 40),
+                                    0.0, 0.1, 1, None) == C.ERR_INVALID
+    assert C.lib().chemora_fill_ghosts(g.handle, ctypes.c_void_p(4096), 0.0, None) == C.OK
+
+
+def test_constraints_unsupported_for_wave():
+    g = C.Grid((8, 8, 8), 2, 0.1, system=C.WAVE)
+    st = C.lib().chemora_constraints(g.handle, ctypes.c_void_p(4096), None,
+                                     ctypes.c_void_p(8192), ctypes.c_void_p(1 << 20), None)
+    assert st == C.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n,g,system", [((128, 128, 128), 3, C.BSSN), ((37, 29, 19), 2, C.WAVE),
+                                        ((5, 3, 4), 3, C.BSSN)])
+def test_layout(n, g, system):
+    gr = C.Grid(n, g, 0.1, system=system, boundary=C.BC_CALLER)
+    nv = 24 if system == C.BSSN else 2
+    assert gr.nvars == nv
+    sx, sy, sz, sv = gr.strides
+    assert sx == 1
+    # interior x = 0 on a 128-byte boundary, rows 128-byte multiples
+    assert gr.interior_offset % 16 == 0 and sy % 16 == 0
+    assert sy >= n[0] + 2 * g + 16 - g
+    assert sz == sy * (n[1] + 2 * g)
+    assert sv == sz * (n[2] + 2 * g)
+    assert gr.state_elems == nv * sv
+    # the lowest ghost point is still inside the array
+    assert gr.interior_offset - g * (1 + sy + sz) >= 0
+    assert gr.workspace_bytes() == 3 * gr.state_elems * 8
+
+
+def test_batch_meta_bytes_rejects_empty():
+    assert C.batch_meta_bytes(0) == -1
