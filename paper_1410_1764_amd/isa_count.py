@@ -1,0 +1,90 @@
+"""Static operation count of the BSSN right-hand-side kernels.
+
+Compiles bssn.hip for gfx950 to assembly (device side only) and counts the
+floating-point vector instructions of the right-hand-side-only kernels.  The
+per-point code is branch-free, so the static count is the number executed
+per grid point (plus a handful of index operations outside the point loop).
+FLOPs: v_fma/v_fmac = 2; add, sub, mul, ldexp (a multiply by a power of two),
+rcp and sqrt = 1; conversions and selects are not counted.
+
+Writes profiles/bssn_rhs_flops.json (read by bench.py for the ALU roofline).
+Usage: python -m paper_1410_1764_amd.isa_count
+"""
+from __future__ import annotations
+
+import json
+import os
+import re
+import subprocess
+
+from . import build as B
+
+OPS = {
+    "f64": {"v_fma_f64": 2, "v_fmac_f64": 2, "v_mul_f64": 1, "v_add_f64": 1,
+            "v_rcp_f64": 1, "v_sqrt_f64": 1, "v_div_fmas_f64": 2, "v_div_scale_f64": 0,
+            "v_div_fixup_f64": 0, "v_ldexp_f64": 1},
+    "f32": {"v_fma_f32": 2, "v_fmac_f32": 2, "v_mul_f32": 1, "v_add_f32": 1, "v_sub_f32": 1,
+            "v_subrev_f32": 1, "v_rcp_f32": 1, "v_sqrt_f32": 1, "v_fmamk_f32": 2,
+            "v_fmaak_f32": 2, "v_mac_f32": 2, "v_div_fmas_f32": 2, "v_ldexp_f32": 1},
+}
+
+
+def kernel_bodies(asm: str):
+    starts = [(m.start(), m.group(1)) for m in re.finditer(r"^(_Z\S+):", asm, re.M)]
+    for q, (pos, name) in enumerate(starts):
+        end = starts[q + 1][0] if q + 1 < len(starts) else len(asm)
+        yield name, asm[pos:end]
+
+
+def count(body: str):
+    res = {}
+    for kind, table in OPS.items():
+        n_instr = {}
+        flops = 0
+        for op, w in table.items():
+            c = len(re.findall(r"^\s+" + op + r"(_e32|_e64|_dpp|_sdwa)?\s", body, re.M))
+            if c:
+                n_instr[op] = c
+                flops += w * c
+        res[kind] = {"instructions": n_instr, "flops_per_point": flops}
+    res["global_load"] = len(re.findall(r"^\s+global_load", body, re.M))
+    res["scratch"] = len(re.findall(r"^\s+scratch_", body, re.M))
+    return res
+
+
+def main():
+    os.makedirs(B.BUILD, exist_ok=True)
+    out_s = os.path.join(B.BUILD, "bssn_device.s")
+    cmd = [B.HIPCC, *B.CFLAGS, "--offload-device-only", "-S", "-o", out_s,
+           os.path.join(B.CSRC, "bssn.hip")]
+    subprocess.check_call(cmd)
+    asm = open(out_s).read()
+    result = {"source": "paper_1410_1764_amd/csrc/bssn.hip", "arch": B.ARCH,
+              "command": "python -m paper_1410_1764_amd.isa_count"}
+    for name, body in kernel_bodies(asm):
+        if "bssn_stage_kernelILi0EdE" in name:
+            c = count(body)
+            result["fp64"] = {"kernel": name, "flops_per_point": c["f64"]["flops_per_point"],
+                              "instructions": c["f64"]["instructions"],
+                              "global_loads": c["global_load"], "scratch_ops": c["scratch"]}
+        if "bssn_stage_kernelILi0EfE" in name:
+            c = count(body)
+            result["mixed"] = {"kernel": name, "f32_flops_per_point": c["f32"]["flops_per_point"],
+                               "f64_flops_per_point": c["f64"]["flops_per_point"],
+                               "instructions": {**c["f32"]["instructions"],
+                                                **c["f64"]["instructions"]},
+                               "global_loads": c["global_load"], "scratch_ops": c["scratch"]}
+    path = os.path.join(B.ROOT, "profiles", "bssn_rhs_flops.json")
+    old = {}
+    if os.path.exists(path):
+        old = json.load(open(path))
+    for k in ("traffic_fp64_bytes_per_launch", "traffic_note"):
+        if k in old:
+            result[k] = old[k]
+    with open(path, "w") as f:
+        json.dump(result, f, indent=1)
+    print(json.dumps(result, indent=1))
+
+
+if __name__ == "__main__":
+    main()
