@@ -85,7 +85,9 @@ __device__ __forceinline__ void gaugewave_values(const BssnPar& P, double xa, do
     }
   }
   v[7] = -(pi * A / d) * c * exp(-1.5 * L);
-  v[14 + a] = -(4.0 * pi * A / (3.0 * d)) * c * exp(-5.0 * L / 3.0);
+  const double gam = -(4.0 * pi * A / (3.0 * d)) * c * exp(-5.0 * L / 3.0);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) v[14 + b] = b == a ? gam : 0.0;  // constant indices
   v[17] = sqrt(H);
 }
 
