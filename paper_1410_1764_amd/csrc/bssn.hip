@@ -22,8 +22,15 @@ struct BssnArgs {
   int images;
 };
 
+// CHEMORA_BSSN_WAVES: minimum waves per SIMD the register allocator must
+// allow (an ablation switch; 1 lets the FP64 kernel use VGPRs + AGPRs).
+#ifndef CHEMORA_BSSN_WAVES
+#define CHEMORA_BSSN_WAVES 1
+#endif
+
 template <int STAGE, typename T>
-__global__ void __launch_bounds__(256) bssn_stage_kernel(BssnArgs a) {
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(CHEMORA_BSSN_WAVES))) bssn_stage_kernel(BssnArgs a) {
   const Geo& G = a.G;
   const int nb = a.tiles[0] * a.tiles[1] * a.tiles[2];
   const int b = xcd_tile(blockIdx.x, nb);

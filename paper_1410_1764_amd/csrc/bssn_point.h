@@ -51,6 +51,12 @@ enum : int {
 // rewrite x in a VGPR: the value must exist at that point, so the
 // arithmetic producing it cannot sink below the next group's loads, which
 // in turn cannot rise above the memory fence.  No instruction is emitted.
+// CHEMORA_BSSN_FENCE selects the policy (an ablation switch; every level
+// computes the same values): 2 = fence after every stencil group (default),
+// 1 = fence once per grid function, 0 = no fences.
+#ifndef CHEMORA_BSSN_FENCE
+#define CHEMORA_BSSN_FENCE 2
+#endif
 template <typename T>
 __device__ __forceinline__ void pin(T& x) {
   asm volatile("" : "+v"(x));
@@ -106,18 +112,20 @@ __device__ __forceinline__ void axis_derivs(const double* __restrict__ f, const 
       adv += beta[d] * l;
     }
   }
-  if (D1) {
-    pin(d1[0]);
-    pin(d1[1]);
-    pin(d1[2]);
+  if (CHEMORA_BSSN_FENCE >= 2 || (CHEMORA_BSSN_FENCE == 1 && !D2)) {
+    if (D1) {
+      pin(d1[0]);
+      pin(d1[1]);
+      pin(d1[2]);
+    }
+    if (D2) {
+      pin(d2[0]);
+      pin(d2[1]);
+      pin(d2[2]);
+    }
+    if (ADV) pin(adv);
+    fence_memory();
   }
-  if (D2) {
-    pin(d2[0]);
-    pin(d2[1]);
-    pin(d2[2]);
-  }
-  if (ADV) pin(adv);
-  fence_memory();
 }
 
 // Mixed derivative d_a d_b f: first-derivative stencil along both axes,
@@ -145,10 +153,15 @@ __device__ __forceinline__ void second_derivs(const double* __restrict__ f, cons
   dd[1] = mixed_deriv<T>(f, st[0], st[1], w.i144[0]);
   dd[2] = mixed_deriv<T>(f, st[0], st[2], w.i144[1]);
   dd[4] = mixed_deriv<T>(f, st[1], st[2], w.i144[2]);
-  pin(dd[1]);
-  pin(dd[2]);
-  pin(dd[4]);
-  fence_memory();
+  if (CHEMORA_BSSN_FENCE >= 1) {
+    pin(dd[0]);
+    pin(dd[1]);
+    pin(dd[2]);
+    pin(dd[3]);
+    pin(dd[4]);
+    pin(dd[5]);
+    fence_memory();
+  }
 }
 
 // Geometry shared by the right-hand side and the constraints: inverse

@@ -106,3 +106,40 @@ def test_layout(n, g, system):
 
 def test_batch_meta_bytes_rejects_empty():
     assert C.batch_meta_bytes(0) == -1
+
+
+def _bssn_gw(n=(24, 24, 24), precision=C.FP64):
+    return C.Grid(n, 3, 1 / 64, system=C.BSSN, precision=precision, boundary=C.BC_GAUGEWAVE,
+                  slicing=C.SLICING_HARMONIC, shift=C.SHIFT_FROZEN)
+
+
+def test_batch_argument_validation():
+    L = C.lib()
+    g1, g2 = _bssn_gw(), _bssn_gw(precision=C.MIXED)
+    arr = (C.Patch * 2)()
+    for q, g in enumerate((g1, g2)):
+        arr[q].grid = g.handle.value
+        arr[q].state = 4096 * (q + 1) * 1024
+        arr[q].workspace = 4096 * (q + 5) * 1024
+    meta = ctypes.c_void_p(1 << 30)
+    assert L.chemora_batch_step(None, 2, meta, 0.0, 0.1, 1, None) == C.ERR_INVALID
+    assert L.chemora_batch_step(arr, 0, meta, 0.0, 0.1, 1, None) == C.ERR_INVALID
+    assert L.chemora_batch_step(arr, 2, meta, 0.0, 0.1, 1, None) == C.ERR_INVALID
+    assert "precision" in C.last_error()
+    assert L.chemora_batch_step(arr, 1, None, 0.0, 0.1, 1, None) == C.ERR_INVALID
+    assert L.chemora_batch_step(arr, 1, meta, 0.0, 0.1, -1, None) == C.ERR_INVALID
+    wave = C.Grid((8, 8, 8), 2, 0.1, system=C.WAVE)
+    arr[1].grid = wave.handle.value
+    assert L.chemora_batch_step(arr, 2, meta, 0.0, 0.1, 1, None) == C.ERR_INVALID
+    assert "gauge-wave" in C.last_error()
+    arr[1].state = 0
+    assert L.chemora_batch_step(arr, 2, meta, 0.0, 0.1, 1, None) == C.ERR_INVALID
+    assert L.chemora_autotune(arr, 0, meta, None) == C.ERR_INVALID
+    assert C.batch_meta_bytes(64) > 64 * 200
+    assert C.batch_meta_bytes(64) % 256 == 0
+
+
+def test_batch_tile_model():
+    t = C.batch_tile((96, 90, 80))
+    assert t[0] * t[1] == 256 and t[2] >= 1
+    assert C.batch_tile((24, 30, 40))[0] <= 32  # narrow patches get narrow tiles
