@@ -102,8 +102,9 @@ int validate_desc(const chemora_grid_desc* d) {
   const long long e0 = d->n[0] + 2LL * d->ghost, e1 = d->n[1] + 2LL * d->ghost;
   const long long e2 = d->n[2] + 2LL * d->ghost;
   const long long sy = ((kAlign + d->n[0] + d->ghost + kAlign - 1) / kAlign) * kAlign;
-  if (sy * e1 > (1LL << 30) || sy * e1 * e2 > (1LL << 40) || e0 <= 0)
-    return fail(CHEMORA_ERR_INVALID, "grid too large");
+  // one grid function must be addressable with 32-bit element offsets
+  if (sy * e1 * e2 > (1LL << 31) - 1 || e0 <= 0)
+    return fail(CHEMORA_ERR_INVALID, "grid too large: one grid function exceeds 2^31 elements");
   return CHEMORA_OK;
 }
 

@@ -195,11 +195,11 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
       const int i = tx * p.ltx + lx, j = ty * p.lty + ly;
       if (ly < p.lty && i < G.n[0] && j < G.n[1]) {
         const int k0 = tzi * p.tz, k1 = min(k0 + p.tz, G.n[2]);
-        const long long st[3] = {1, G.sy, G.sz};
         for (int k = k0; k < k1; ++k) {
           const long long q = i + (long long)j * G.sy + (long long)k * G.sz;
           T rhs[V_N];
-          bssn_rhs_point<T>(io.yin + G.off0 + q, G.sv, st, p.W, p.P, rhs);
+          GSrc src{io.yin + G.off0 + q, G.sv, G.sy, G.sz};
+          bssn_rhs_point<T>(src, p.W, p.P, rhs);
           bssn_store<STAGE, T>(io, G, q, i, j, k, rhs, false);
         }
       }

@@ -5,9 +5,16 @@
 // Mapping: a workgroup of 256 threads covers a tile of ltx x lty points in
 // xy (ltx = 64, 32 or 16; x contiguous within a wavefront so that every
 // stencil load of a wavefront is a coalesced row segment) and marches zc
-// planes along z, one point per thread per plane.  Stencil neighbours come
-// from the L1/L2 caches.  Tiles are laid out XCD-contiguously (xcd_tile).
-#include "bssn_point.h"
+// planes along z, one point per thread per plane.  Tiles are laid out
+// XCD-contiguously (xcd_tile).  Two kernels:
+//   bssn_lds_kernel (default): each grid function's tile neighbourhood is
+//     staged in LDS by one cooperative, double-buffered burst (bssn_lds.h);
+//   bssn_stage_kernel (ablation, CHEMORA_BSSN_KERNEL=global): stencil
+//     neighbours are read straight from global memory through L1/L2.
+#include <cstdlib>
+#include <cstring>
+
+#include "bssn_lds.h"
 
 namespace chemora {
 namespace {
@@ -40,24 +47,72 @@ __attribute__((amdgpu_waves_per_eu(CHEMORA_BSSN_WAVES))) bssn_stage_kernel(BssnA
   const int j = by * a.lty + (int)threadIdx.x / a.ltx;
   if (i >= G.n[0] || j >= G.n[1]) return;
   const int k0 = bz * a.zc, k1 = min(k0 + a.zc, G.n[2]);
-  const long long st[3] = {1, G.sy, G.sz};
   for (int k = k0; k < k1; ++k) {
     const long long p = i + (long long)j * G.sy + (long long)k * G.sz;
     T rhs[V_N];
-    bssn_rhs_point<T>(a.io.yin + G.off0 + p, G.sv, st, a.W, a.P, rhs);
+    GSrc src{a.io.yin + G.off0 + p, G.sv, G.sy, G.sz};
+    bssn_rhs_point<T>(src, a.W, a.P, rhs);
     bssn_store<STAGE, T>(a.io, G, p, i, j, k, rhs, a.images != 0);
+  }
+}
+
+template <int STAGE, typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) bssn_lds_kernel(BssnArgs a) {
+  using S = LdsShape<TX, TY>;
+  __shared__ double lds[2 * S::TOTAL];
+  const Geo& G = a.G;
+  const int nb = a.tiles[0] * a.tiles[1] * a.tiles[2];
+  const int b = xcd_tile(blockIdx.x, nb);
+  const int bx = b % a.tiles[0], by = (b / a.tiles[0]) % a.tiles[1];
+  const int bz = b / (a.tiles[0] * a.tiles[1]);
+  const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
+  const int x0 = bx * TX, y0 = by * TY;
+  const int i = x0 + tx, j = y0 + ty;
+  const bool active = i < G.n[0] && j < G.n[1];
+  const int k0 = bz * a.zc, k1 = min(k0 + a.zc, G.n[2]);
+  LSrc<TX, TY> src;
+  src.init(G, a.io.yin, lds, x0, y0, k0, tx, ty);
+  src.prefetch(kRhsOrder[0]);
+  for (int k = k0; k < k1; ++k) {
+    src.more = k + 1 < k1;
+    T rhs[V_N];
+    bssn_rhs_point<T>(src, a.W, a.P, rhs);
+    if (active)
+      bssn_store<STAGE, T>(a.io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
+                           a.images != 0);
+    src.next_plane();
+  }
+}
+
+bool use_global_kernel() {
+  static const bool g = [] {
+    const char* e = std::getenv("CHEMORA_BSSN_KERNEL");
+    return e && std::strcmp(e, "global") == 0;
+  }();
+  return g;
+}
+
+template <int STAGE, typename T>
+void launch_shape(const BssnArgs& a, dim3 grid, hipStream_t s) {
+  if (use_global_kernel()) {
+    hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T>), grid, dim3(256), 0, s, a);
+  } else if (a.ltx == 64) {
+    hipLaunchKernelGGL((bssn_lds_kernel<STAGE, T, 64, 4>), grid, dim3(256), 0, s, a);
+  } else if (a.ltx == 32) {
+    hipLaunchKernelGGL((bssn_lds_kernel<STAGE, T, 32, 8>), grid, dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((bssn_lds_kernel<STAGE, T, 16, 16>), grid, dim3(256), 0, s, a);
   }
 }
 
 template <typename T>
 hipError_t launch_t(int stage, const BssnArgs& a, dim3 grid, hipStream_t s) {
-  const dim3 block(256);
   switch (stage) {
-    case 0: hipLaunchKernelGGL((bssn_stage_kernel<0, T>), grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((bssn_stage_kernel<1, T>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((bssn_stage_kernel<2, T>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((bssn_stage_kernel<3, T>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((bssn_stage_kernel<4, T>), grid, block, 0, s, a); break;
+    case 0: launch_shape<0, T>(a, grid, s); break;
+    case 1: launch_shape<1, T>(a, grid, s); break;
+    case 2: launch_shape<2, T>(a, grid, s); break;
+    case 3: launch_shape<3, T>(a, grid, s); break;
+    default: launch_shape<4, T>(a, grid, s); break;
   }
   return hipGetLastError();
 }
@@ -77,7 +132,9 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
   a.tiles[0] = (G.n[0] + a.ltx - 1) / a.ltx;
   a.tiles[1] = (G.n[1] + a.lty - 1) / a.lty;
   const long long xy = (long long)a.tiles[0] * a.tiles[1];
-  const long long want = 8192;  // workgroups: many per CU so that tails are short
+  // workgroups: several rounds of one per CU; the LDS kernel amortises its
+  // set-up and prefetches the next plane when it marches a few planes
+  const long long want = use_global_kernel() ? 8192 : 2048;
   int zsplit = (int)((want + xy - 1) / xy);
   if (zsplit > G.n[2]) zsplit = G.n[2];
   if (zsplit < 1) zsplit = 1;

@@ -1,0 +1,154 @@
+// bssn_lds.h -- LDS-staged source for the BSSN point code (bssn_point.h).
+//
+// A workgroup of TX*TY threads evaluates one TX x TY tile of a z-plane (one
+// point per thread) and marches along z.  The 24 grid functions are
+// differentiated one after another (kRhsOrder); for each one the workgroup
+// stages the tile's stencil neighbourhood in LDS with one cooperative burst
+// of loads, and every thread then reads its ~70 stencil values from LDS
+// (low latency, no L1 traffic) instead of from the caches.
+//
+// Neighbourhood of a TX x TY tile at plane k (union of the stencils of its
+// points): plane k with a 3-point halo in x and y (axis and lopsided
+// stencils, xy mixed derivatives); planes k+-1 and k+-2 with a 2-point halo
+// (xz and yz mixed derivatives, z axis); planes k+-3 without halo (z
+// lopsided).  For 64 x 4 that is 700 + 4*544 + 2*256 = 3388 doubles.
+//
+// Double buffering: while the threads differentiate grid function s from
+// one buffer, the loads of grid function s+1 are already in flight into
+// registers; acquire(s+1) writes them to the other buffer and synchronises.
+// One barrier per grid function.  Out-of-grid tile points (ragged tiles)
+// read clamped addresses; their results are never stored.
+#pragma once
+
+#include "bssn_point.h"
+
+namespace chemora {
+
+template <int TX, int TY>
+struct LdsShape {
+  static constexpr int NT = TX * TY;
+  static constexpr int W0 = TX + 6, H0 = TY + 6;  // plane k, halo 3
+  static constexpr int W1 = TX + 4, H1 = TY + 4;  // planes k+-1, k+-2, halo 2
+  static constexpr int N0 = W0 * H0, N1 = W1 * H1, N3 = TX * TY;
+  // segments in order: k | k+1 | k-1 | k+2 | k-2 | k+3 | k-3
+  static constexpr int TOTAL = N0 + 4 * N1 + 2 * N3;
+  static constexpr int SLOTS = (TOTAL + NT - 1) / NT;
+};
+
+// Accessor into one staged buffer for the thread at tile position (tx, ty).
+template <int TX, int TY>
+struct LAcc {
+  using S = LdsShape<TX, TY>;
+  const double* b0;  // plane k at (tx, ty)
+  const double* b1;  // plane k+1 at (tx, ty); k-1, k+2, k-2 follow at N1 strides
+  const double* b3;  // plane k+3 at (tx, ty); k-3 follows at N3
+  __device__ __forceinline__ double operator()(int dx, int dy, int dz) const {
+    if (dz == 0) return b0[dy * S::W0 + dx];
+    if (dz == 3) return b3[0];
+    if (dz == -3) return b3[S::N3];
+    const int seg = dz == 1 ? 0 : (dz == -1 ? 1 : (dz == 2 ? 2 : 3));
+    return b1[seg * S::N1 + dy * S::W1 + dx];
+  }
+  // +-(dx,dy,dz): in-plane (x or y axis) or the z axis at distance 3
+  __device__ __forceinline__ double sel(bool up, int dx, int dy, int dz) const {
+    if (dz == 0) {
+      const int o = dy * S::W0 + dx;
+      return b0[up ? o : -o];
+    }
+    return b3[up ? 0 : S::N3];
+  }
+};
+
+template <int TX, int TY>
+struct LSrc {
+  using S = LdsShape<TX, TY>;
+  double* lds;       // 2 * TOTAL doubles
+  const double* Yt;  // yin + off0: tile addressing base (variable 0)
+  const double* Yc;  // centre value of variable 0 at the thread's (clamped) point
+  long long sv, sz;
+  int off[S::SLOTS];     // element offset of each staged slot (variable 0)
+  double reg[S::SLOTS];  // loads in flight for the next grid function
+  int b0o, b1o, b3o;     // the thread's element offsets inside one buffer
+  int seq;               // grid functions acquired at this point so far
+  bool more;             // another plane follows
+
+  // tile origin (x0, y0), plane k, thread position (tx, ty)
+  __device__ __forceinline__ void init(const Geo& G, const double* yin, double* shared, int x0,
+                                       int y0, int k, int tx, int ty) {
+    lds = shared;
+    Yt = yin + G.off0;
+    sv = G.sv;
+    sz = G.sz;
+    const int tid = ty * TX + tx;
+#pragma unroll
+    for (int m = 0; m < S::SLOTS; ++m) {
+      int t = tid + m * S::NT;
+      if (t >= S::TOTAL) t = 0;  // beyond the buffer: load slot 0 again, never stored
+      int px, py, dz;
+      if (t < S::N0) {
+        dz = 0;
+        py = t / S::W0 - 3;
+        px = t % S::W0 - 3;
+      } else if (t < S::N0 + 4 * S::N1) {
+        const int r = t - S::N0, s = r / S::N1, q = r % S::N1;
+        dz = (s == 0) ? 1 : (s == 1 ? -1 : (s == 2 ? 2 : -2));
+        py = q / S::W1 - 2;
+        px = q % S::W1 - 2;
+      } else {
+        const int r = t - S::N0 - 4 * S::N1, s = r / S::N3, q = r % S::N3;
+        dz = s == 0 ? 3 : -3;
+        py = q / TX;
+        px = q % TX;
+      }
+      int gx = x0 + px, gy = y0 + py;
+      gx = gx < -G.g ? -G.g : (gx > G.n[0] + G.g - 1 ? G.n[0] + G.g - 1 : gx);
+      gy = gy < -G.g ? -G.g : (gy > G.n[1] + G.g - 1 ? G.n[1] + G.g - 1 : gy);
+      off[m] = gx + gy * G.sy + (k + dz) * G.sz;
+    }
+    b0o = (ty + 3) * S::W0 + tx + 3;
+    b1o = S::N0 + (ty + 2) * S::W1 + tx + 2;
+    b3o = S::N0 + 4 * S::N1 + ty * TX + tx;
+    const int ci = x0 + tx < G.n[0] ? x0 + tx : G.n[0] - 1;
+    const int cj = y0 + ty < G.n[1] ? y0 + ty : G.n[1] - 1;
+    Yc = Yt + ci + (long long)cj * G.sy + (long long)k * G.sz;
+    seq = 0;
+    more = false;
+  }
+
+  __device__ __forceinline__ void prefetch(int v) {
+    const double* base = Yt + v * sv;
+#pragma unroll
+    for (int m = 0; m < S::SLOTS; ++m) reg[m] = base[off[m]];
+  }
+
+  __device__ __forceinline__ double center(int v) const { return Yc[v * sv]; }
+
+  // the staged neighbourhood of grid function kRhsOrder[seq] (== v)
+  __device__ __forceinline__ LAcc<TX, TY> acquire(int /*v*/) {
+    double* buf = lds + (seq & 1) * S::TOTAL;
+    const int tid = (int)threadIdx.x;
+#pragma unroll
+    for (int m = 0; m < S::SLOTS; ++m) {
+      const int t = tid + m * S::NT;
+      if (m < S::SLOTS - 1 || t < S::TOTAL) buf[t] = reg[m];
+    }
+    __syncthreads();
+    if (seq + 1 < V_N) {
+      prefetch(kRhsOrder[seq + 1]);
+    } else if (more) {  // first grid function of the next plane
+#pragma unroll
+      for (int m = 0; m < S::SLOTS; ++m) off[m] += (int)sz;
+      prefetch(kRhsOrder[0]);
+    }
+    ++seq;
+    return LAcc<TX, TY>{buf + b0o, buf + b1o, buf + b3o};
+  }
+
+  // move to the next plane (after the last acquire of this one)
+  __device__ __forceinline__ void next_plane() {
+    Yc += sz;
+    seq = 0;
+  }
+};
+
+}  // namespace chemora

@@ -43,8 +43,6 @@ enum : int {
   V_N = 24
 };
 
-// index of the symmetric pair (i, j) in (xx, xy, xz, yy, yz, zz); closed
-// form so that it folds to a constant inside unrolled loops
 // Scheduling fences.  Without them the compiler issues the ~700 stencil
 // loads of a point ahead of the arithmetic that consumes them and spills
 // several KB per lane to scratch.  pin() is an empty asm that claims to
@@ -63,6 +61,8 @@ __device__ __forceinline__ void pin(T& x) {
 }
 __device__ __forceinline__ void fence_memory() { asm volatile("" ::: "memory"); }
 
+// index of the symmetric pair (i, j) in (xx, xy, xz, yy, yz, zz); closed
+// form so that it folds to a constant inside unrolled loops
 __host__ __device__ constexpr int sidx(int i, int j) {
   return (i < j ? i : j) * (5 - (i < j ? i : j)) / 2 + (i < j ? j : i);
 }
@@ -86,26 +86,55 @@ inline Weights make_weights(const double h[3]) {
   return w;
 }
 
+// Stencil accessors.  A grid function's neighbourhood is read through an
+// accessor f(dx, dy, dz) (offsets from the point; compile-time constants
+// once the loops are unrolled) and f.sel(up, dx, dy, dz), the value at
+// +(dx,dy,dz) if up else at -(dx,dy,dz) (one load through a selected
+// address).  GAcc reads global memory; the LDS tile accessor is in
+// bssn_lds.h.
+struct GAcc {
+  const double* f;  // centre value
+  long long sy, sz;
+  __device__ __forceinline__ double operator()(int dx, int dy, int dz) const {
+    return f[dx + dy * sy + dz * sz];
+  }
+  __device__ __forceinline__ double sel(bool up, int dx, int dy, int dz) const {
+    const long long o = dx + dy * sy + dz * sz;
+    return f[up ? o : -o];
+  }
+};
+
+// Source of all 24 grid functions at one point, reading global memory:
+// center(v) is the value of variable v at the point, acquire(v) the
+// accessor of its neighbourhood.  Sources are acquired in a fixed order
+// (the LDS source stages them one by one).
+struct GSrc {
+  const double* Y;  // centre value of variable 0
+  long long sv, sy, sz;
+  __device__ __forceinline__ double center(int v) const { return Y[v * sv]; }
+  __device__ __forceinline__ GAcc acquire(int v) { return GAcc{Y + v * sv, sy, sz}; }
+};
+
 // Centred first derivatives (D1), pure second derivatives (D2) and the
 // advection term beta^k d_k f with the lopsided stencil on the upwind side
-// (ADV) of one grid function; f points at the centre value.
-template <typename T, bool D1, bool D2, bool ADV>
-__device__ __forceinline__ void axis_derivs(const double* __restrict__ f, const long long st[3],
-                                            const Weights& w, const bool bpos[3],
+// (ADV) of one grid function.
+template <typename T, bool D1, bool D2, bool ADV, typename Acc>
+__device__ __forceinline__ void axis_derivs(const Acc& f, const Weights& w, const bool bpos[3],
                                             const T beta[3], T d1[3], T d2[3], T& adv) {
-  const double f0 = f[0];
+  const double f0 = f(0, 0, 0);
   adv = (T)0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const long long s = st[d];
-    const double m1 = f[-s], p1 = f[s], m2 = f[-2 * s], p2 = f[2 * s];
+    const int ex = d == 0, ey = d == 1, ez = d == 2;
+    const double m1 = f(-ex, -ey, -ez), p1 = f(ex, ey, ez);
+    const double m2 = f(-2 * ex, -2 * ey, -2 * ez), p2 = f(2 * ex, 2 * ey, 2 * ez);
     if (D1) d1[d] = ((T)8 * (T)(p1 - m1) - (T)(p2 - m2)) * (T)w.i12h[d];
     if (D2)
       d2[d] = ((T)16 * (T)((p1 - f0) + (m1 - f0)) - (T)((p2 - f0) + (m2 - f0))) * (T)w.i12hh[d];
     if (ADV) {
       const bool up = bpos[d];
       const double u1 = up ? p1 : m1, um1 = up ? m1 : p1, u2 = up ? p2 : m2;
-      const double u3 = f[up ? 3 * s : -3 * s];
+      const double u3 = f.sel(up, 3 * ex, 3 * ey, 3 * ez);
       T l = ((T)18 * (T)(u1 - f0) - (T)3 * (T)(um1 - f0) - (T)6 * (T)(u2 - f0) + (T)(u3 - f0)) *
             (T)w.i12h[d];
       l = up ? l : -l;
@@ -128,31 +157,34 @@ __device__ __forceinline__ void axis_derivs(const double* __restrict__ f, const 
   }
 }
 
-// Mixed derivative d_a d_b f: first-derivative stencil along both axes,
-// q_mn = [f(m,n) - f(-m,n)] - [f(m,-n) - f(-m,-n)], weights 8 / -1.
-template <typename T>
-__device__ __forceinline__ T mixed_deriv(const double* __restrict__ f, long long sa, long long sb,
-                                         double wab) {
+// Mixed derivative d_a d_b f (a < b): first-derivative stencil along both
+// axes, q_mn = [f(m,n) - f(-m,n)] - [f(m,-n) - f(-m,-n)], weights 8 / -1.
+template <typename T, typename Acc>
+__device__ __forceinline__ T mixed_deriv(const Acc& f, int a, int b, double wab) {
+  // value at alpha e_a + beta e_b
+  auto at = [&](int alpha, int beta) {
+    return f(alpha * (a == 0) + beta * (b == 0), alpha * (a == 1) + beta * (b == 1),
+             alpha * (a == 2) + beta * (b == 2));
+  };
   double q[2][2];
 #pragma unroll
   for (int m = 1; m <= 2; ++m)
 #pragma unroll
     for (int n = 1; n <= 2; ++n)
-      q[m - 1][n - 1] =
-          (f[m * sa + n * sb] - f[-m * sa + n * sb]) - (f[m * sa - n * sb] - f[-m * sa - n * sb]);
+      q[m - 1][n - 1] = (at(m, n) - at(-m, n)) - (at(m, -n) - at(-m, -n));
   return ((T)64 * (T)q[0][0] - (T)8 * (T)q[0][1] - (T)8 * (T)q[1][0] + (T)q[1][1]) * (T)wab;
 }
 
 // All six second derivatives d_a d_b f in symmetric order.
-template <typename T>
-__device__ __forceinline__ void second_derivs(const double* __restrict__ f, const long long st[3],
-                                              const Weights& w, const T d2pure[3], T dd[6]) {
+template <typename T, typename Acc>
+__device__ __forceinline__ void second_derivs(const Acc& f, const Weights& w, const T d2pure[3],
+                                              T dd[6]) {
   dd[0] = d2pure[0];
   dd[3] = d2pure[1];
   dd[5] = d2pure[2];
-  dd[1] = mixed_deriv<T>(f, st[0], st[1], w.i144[0]);
-  dd[2] = mixed_deriv<T>(f, st[0], st[2], w.i144[1]);
-  dd[4] = mixed_deriv<T>(f, st[1], st[2], w.i144[2]);
+  dd[1] = mixed_deriv<T>(f, 0, 1, w.i144[0]);
+  dd[2] = mixed_deriv<T>(f, 0, 2, w.i144[1]);
+  dd[4] = mixed_deriv<T>(f, 1, 2, w.i144[2]);
   if (CHEMORA_BSSN_FENCE >= 1) {
     pin(dd[0]);
     pin(dd[1]);
@@ -168,14 +200,11 @@ __device__ __forceinline__ void second_derivs(const double* __restrict__ f, cons
 // conformal metric gu, Christoffels cdu (Gt^i_jk) and their contraction Gd,
 // d_i chi, and the Ricci tensor R_ij (conformal part + chi part).  With ADV
 // the advection terms of gt_ij, Gamt^i and chi are written to rhs as well.
-template <typename T, bool ADV>
-__device__ __forceinline__ void bssn_geometry(const double* __restrict__ Y, long long sv,
-                                              const long long st[3], const Weights& w,
-                                              const bool bpos[3], const T beta[3], T chi,
-                                              const T gt[6], T gu[6], T cdu[3][6], T Gd[3],
-                                              T dchi[3], T R[6], T rhs[V_N]) {
-  auto F = [&](int v) { return Y + v * sv; };
-
+template <typename T, bool ADV, typename Src>
+__device__ __forceinline__ void bssn_geometry(Src& src, const Weights& w, const bool bpos[3],
+                                              const T beta[3], T chi, const T gt[6], T gu[6],
+                                              T cdu[3][6], T Gd[3], T dchi[3], T R[6],
+                                              T rhs[V_N]) {
   // ---- inverse conformal metric (adjugate / determinant)
   {
     const T c00 = gt[3] * gt[5] - gt[4] * gt[4];
@@ -200,10 +229,10 @@ __device__ __forceinline__ void bssn_geometry(const double* __restrict__ Y, long
   // R_ij = -1/2 gt^lm d_l d_m gt_ij right away; advection
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    const double* f = F(V_GT + q);
-    axis_derivs<T, true, true, ADV>(f, st, w, bpos, beta, dgt[q], dpure, adv);
+    const auto f = src.acquire(V_GT + q);
+    axis_derivs<T, true, true, ADV>(f, w, bpos, beta, dgt[q], dpure, adv);
     if (ADV) rhs[V_GT + q] = adv;
-    second_derivs<T>(f, st, w, dpure, dd);
+    second_derivs<T>(f, w, dpure, dd);
     R[q] = (T)(-0.5) * (gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
                         (T)2 * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]));
   }
@@ -235,7 +264,7 @@ __device__ __forceinline__ void bssn_geometry(const double* __restrict__ Y, long
     T dG[3][3];  // dG[k][j] = d_j Gt^k
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      axis_derivs<T, true, false, ADV>(F(V_GAM + k), st, w, bpos, beta, dG[k], dpure, adv);
+      axis_derivs<T, true, false, ADV>(src.acquire(V_GAM + k), w, bpos, beta, dG[k], dpure, adv);
       if (ADV) rhs[V_GAM + k] = adv;
     }
 #pragma unroll
@@ -276,9 +305,10 @@ __device__ __forceinline__ void bssn_geometry(const double* __restrict__ Y, long
 
   // ---- chi: D_i D_j chi = d_i d_j chi - Gt^k_ij d_k chi; chi part of R_ij
   {
-    axis_derivs<T, true, true, ADV>(F(V_CHI), st, w, bpos, beta, dchi, dpure, adv);
+    const auto f = src.acquire(V_CHI);
+    axis_derivs<T, true, true, ADV>(f, w, bpos, beta, dchi, dpure, adv);
     if (ADV) rhs[V_CHI] = adv;
-    second_derivs<T>(F(V_CHI), st, w, dpure, dd);
+    second_derivs<T>(f, w, dpure, dd);
 #pragma unroll
     for (int q = 0; q < 6; ++q)
       dd[q] -= cdu[0][q] * dchi[0] + cdu[1][q] * dchi[1] + cdu[2][q] * dchi[2];
@@ -301,35 +331,38 @@ __device__ __forceinline__ void bssn_geometry(const double* __restrict__ Y, long
   }
 }
 
-// Right-hand side of all 24 variables at one point.  Y points at the centre
-// value of variable 0; variables are sv apart.
-template <typename T>
-__device__ __forceinline__ void bssn_rhs_point(const double* __restrict__ Y, long long sv,
-                                               const long long st[3], const Weights& w,
-                                               const BssnPar& P, T rhs[V_N]) {
-  auto F = [&](int v) { return Y + v * sv; };
+// Order in which bssn_rhs_point acquires the neighbourhoods of the 24
+// grid functions (a staging source prefetches them in this order).
+__device__ constexpr int kRhsOrder[V_N] = {
+    V_GT + 0, V_GT + 1, V_GT + 2, V_GT + 3, V_GT + 4, V_GT + 5, V_GAM + 0, V_GAM + 1,
+    V_GAM + 2, V_CHI, V_ALP, V_BETA + 0, V_BETA + 1, V_BETA + 2, V_TRK, V_AT + 0,
+    V_AT + 1, V_AT + 2, V_AT + 3, V_AT + 4, V_AT + 5, V_B + 0, V_B + 1, V_B + 2};
 
+// Right-hand side of all 24 variables at one point, reading through src.
+template <typename T, typename Src>
+__device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const BssnPar& P,
+                                               T rhs[V_N]) {
   // ---- centre values, upwind sides
   bool bpos[3];
   T beta[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const double b = F(V_BETA + d)[0];
+    const double b = src.center(V_BETA + d);
     bpos[d] = b >= 0.0;
     beta[d] = (T)b;
   }
-  const T chi = (T)F(V_CHI)[0];
-  const T trK = (T)F(V_TRK)[0];
-  const T alpha = (T)F(V_ALP)[0];
+  const T chi = (T)src.center(V_CHI);
+  const T trK = (T)src.center(V_TRK);
+  const T alpha = (T)src.center(V_ALP);
   T gt[6], At[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    gt[q] = (T)F(V_GT + q)[0];
-    At[q] = (T)F(V_AT + q)[0];
+    gt[q] = (T)src.center(V_GT + q);
+    At[q] = (T)src.center(V_AT + q);
   }
 
   T gu[6], cdu[3][6], Gd[3], dchi[3], R[6];
-  bssn_geometry<T, true>(Y, sv, st, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, rhs);
+  bssn_geometry<T, true>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, rhs);
   T dd[6], dpure[3], d1v[3], adv;
 
   // ---- lapse: D_i D_j alpha with the physical Christoffels
@@ -338,9 +371,10 @@ __device__ __forceinline__ void bssn_rhs_point(const double* __restrict__ Y, lon
   T lapalp;
   T X[6];
   {
-    axis_derivs<T, true, true, true>(F(V_ALP), st, w, bpos, beta, dalp, dpure, adv);
+    const auto f = src.acquire(V_ALP);
+    axis_derivs<T, true, true, true>(f, w, bpos, beta, dalp, dpure, adv);
     rhs[V_ALP] = adv;
-    second_derivs<T>(F(V_ALP), st, w, dpure, dd);
+    second_derivs<T>(f, w, dpure, dd);
     const T i2chi = (T)0.5 / chi;
     T uchi[3];  // gt^kl d_l chi
 #pragma unroll
@@ -388,10 +422,10 @@ __device__ __forceinline__ void bssn_rhs_point(const double* __restrict__ Y, lon
   T lapb[3], gdiv[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double* f = F(V_BETA + k);
-    axis_derivs<T, true, true, true>(f, st, w, bpos, beta, dbeta[k], dpure, adv);
+    const auto f = src.acquire(V_BETA + k);
+    axis_derivs<T, true, true, true>(f, w, bpos, beta, dbeta[k], dpure, adv);
     rhs[V_BETA + k] = adv;
-    second_derivs<T>(f, st, w, dpure, dd);
+    second_derivs<T>(f, w, dpure, dd);
     lapb[k] = gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
               (T)2 * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]);
     // gdiv[j] += d_j d_k beta^k (k fixed here)
@@ -409,16 +443,16 @@ __device__ __forceinline__ void bssn_rhs_point(const double* __restrict__ Y, lon
 
   // ---- trK (first derivatives + advection), At and B (advection only)
   T dK[3];
-  axis_derivs<T, true, false, true>(F(V_TRK), st, w, bpos, beta, dK, dpure, adv);
+  axis_derivs<T, true, false, true>(src.acquire(V_TRK), w, bpos, beta, dK, dpure, adv);
   rhs[V_TRK] = adv;
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    axis_derivs<T, false, false, true>(F(V_AT + q), st, w, bpos, beta, d1v, dpure, adv);
+    axis_derivs<T, false, false, true>(src.acquire(V_AT + q), w, bpos, beta, d1v, dpure, adv);
     rhs[V_AT + q] = adv;
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    axis_derivs<T, false, false, true>(F(V_B + q), st, w, bpos, beta, d1v, dpure, adv);
+    axis_derivs<T, false, false, true>(src.acquire(V_B + q), w, bpos, beta, d1v, dpure, adv);
     rhs[V_B + q] = adv;
   }
 
@@ -464,8 +498,8 @@ __device__ __forceinline__ void bssn_rhs_point(const double* __restrict__ Y, lon
     s += (T)(-2) * aal + (T)2 * alpha * (cA - (T)1.5 * ach * ichi - two3 * gk);
     rhs[V_GAM + i] += s;
     if (P.shift == 1) {
-      rhs[V_BETA + i] += (T)P.F * (T)F(V_B + i)[0];
-      rhs[V_B + i] += s - (T)P.eta * (T)F(V_B + i)[0];
+      rhs[V_BETA + i] += (T)P.F * (T)src.center(V_B + i);
+      rhs[V_B + i] += s - (T)P.eta * (T)src.center(V_B + i);
     } else {
       rhs[V_BETA + i] = (T)0;
       rhs[V_B + i] = (T)0;
