@@ -11,6 +11,7 @@
 //     staged in LDS by one cooperative, double-buffered burst (bssn_lds.h);
 //   bssn_stage_kernel (ablation, CHEMORA_BSSN_KERNEL=global): stencil
 //     neighbours are read straight from global memory through L1/L2.
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 
@@ -69,19 +70,28 @@ __global__ void __launch_bounds__(TX * TY) bssn_lds_kernel(BssnArgs a) {
   const int x0 = bx * TX, y0 = by * TY;
   const int i = x0 + tx, j = y0 + ty;
   const bool active = i < G.n[0] && j < G.n[1];
-  const int k0 = bz * a.zc, k1 = min(k0 + a.zc, G.n[2]);
+  // one plane per workgroup: marching several planes in one workgroup keeps
+  // the staging state live across the loop and roughly doubles the
+  // register footprint
+  const int k = bz;
   LSrc<TX, TY> src;
-  src.init(G, a.io.yin, lds, x0, y0, k0, tx, ty);
+  src.init(G, a.io.yin, lds, x0, y0, k, tx, ty);
   src.prefetch(kRhsOrder[0]);
-  for (int k = k0; k < k1; ++k) {
-    src.more = k + 1 < k1;
-    T rhs[V_N];
-    bssn_rhs_point<T>(src, a.W, a.P, rhs);
-    if (active)
-      bssn_store<STAGE, T>(a.io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
-                           a.images != 0);
-    src.next_plane();
-  }
+  T rhs[V_N];
+  bssn_rhs_point<T>(src, a.W, a.P, rhs);
+  if (active)
+    bssn_store<STAGE, T>(a.io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
+                         a.images != 0);
+}
+
+// CHEMORA_BSSN_TILE=64|32|16 forces the tile width (ablation switch)
+int forced_tile_width() {
+  static const int w = [] {
+    const char* e = std::getenv("CHEMORA_BSSN_TILE");
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 64 || v == 32 || v == 16) ? v : 0;
+  }();
+  return w;
 }
 
 bool use_global_kernel() {
@@ -128,14 +138,15 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
   a.io = io;
   a.images = images ? 1 : 0;
   a.ltx = G.n[0] >= 48 ? 64 : (G.n[0] >= 24 ? 32 : 16);
+  if (forced_tile_width()) a.ltx = forced_tile_width();
   a.lty = 256 / a.ltx;
   a.tiles[0] = (G.n[0] + a.ltx - 1) / a.ltx;
   a.tiles[1] = (G.n[1] + a.lty - 1) / a.lty;
   const long long xy = (long long)a.tiles[0] * a.tiles[1];
-  // workgroups: several rounds of one per CU; the LDS kernel amortises its
-  // set-up and prefetches the next plane when it marches a few planes
-  const long long want = use_global_kernel() ? 8192 : 2048;
-  int zsplit = (int)((want + xy - 1) / xy);
+  // global kernel: enough workgroups for several rounds per CU, each
+  // marching zc planes; LDS kernel: one plane per workgroup
+  const long long want = use_global_kernel() ? 8192 : (long long)1 << 40;
+  int zsplit = (int)std::min<long long>((want + xy - 1) / xy, G.n[2]);
   if (zsplit > G.n[2]) zsplit = G.n[2];
   if (zsplit < 1) zsplit = 1;
   a.zc = (G.n[2] + zsplit - 1) / zsplit;

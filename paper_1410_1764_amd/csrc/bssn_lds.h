@@ -1,7 +1,7 @@
 // bssn_lds.h -- LDS-staged source for the BSSN point code (bssn_point.h).
 //
 // A workgroup of TX*TY threads evaluates one TX x TY tile of a z-plane (one
-// point per thread) and marches along z.  The 24 grid functions are
+// point per thread).  The 24 grid functions are
 // differentiated one after another (kRhsOrder); for each one the workgroup
 // stages the tile's stencil neighbourhood in LDS with one cooperative burst
 // of loads, and every thread then reads its ~70 stencil values from LDS
@@ -36,24 +36,27 @@ struct LdsShape {
 };
 
 // Accessor into one staged buffer for the thread at tile position (tx, ty).
+// The bases point at the low corner of the thread's window, so that every
+// stencil offset is a non-negative constant (ds_read takes an unsigned
+// immediate offset; a negative one would cost an address register each).
 template <int TX, int TY>
 struct LAcc {
   using S = LdsShape<TX, TY>;
-  const double* b0;  // plane k at (tx, ty)
-  const double* b1;  // plane k+1 at (tx, ty); k-1, k+2, k-2 follow at N1 strides
+  const double* b0;  // plane k at (tx - 3, ty - 3)
+  const double* b1;  // plane k+1 at (tx - 2, ty - 2); k-1, k+2, k-2 follow at N1 strides
   const double* b3;  // plane k+3 at (tx, ty); k-3 follows at N3
   __device__ __forceinline__ double operator()(int dx, int dy, int dz) const {
-    if (dz == 0) return b0[dy * S::W0 + dx];
+    if (dz == 0) return b0[(dy + 3) * S::W0 + dx + 3];
     if (dz == 3) return b3[0];
     if (dz == -3) return b3[S::N3];
     const int seg = dz == 1 ? 0 : (dz == -1 ? 1 : (dz == 2 ? 2 : 3));
-    return b1[seg * S::N1 + dy * S::W1 + dx];
+    return b1[seg * S::N1 + (dy + 2) * S::W1 + dx + 2];
   }
   // +-(dx,dy,dz): in-plane (x or y axis) or the z axis at distance 3
   __device__ __forceinline__ double sel(bool up, int dx, int dy, int dz) const {
     if (dz == 0) {
-      const int o = dy * S::W0 + dx;
-      return b0[up ? o : -o];
+      const int c = 3 * S::W0 + 3, o = dy * S::W0 + dx;
+      return b0[up ? c + o : c - o];
     }
     return b3[up ? 0 : S::N3];
   }
@@ -65,12 +68,11 @@ struct LSrc {
   double* lds;       // 2 * TOTAL doubles
   const double* Yt;  // yin + off0: tile addressing base (variable 0)
   const double* Yc;  // centre value of variable 0 at the thread's (clamped) point
-  long long sv, sz;
+  long long sv;
   int off[S::SLOTS];     // element offset of each staged slot (variable 0)
   double reg[S::SLOTS];  // loads in flight for the next grid function
   int b0o, b1o, b3o;     // the thread's element offsets inside one buffer
   int seq;               // grid functions acquired at this point so far
-  bool more;             // another plane follows
 
   // tile origin (x0, y0), plane k, thread position (tx, ty)
   __device__ __forceinline__ void init(const Geo& G, const double* yin, double* shared, int x0,
@@ -78,7 +80,6 @@ struct LSrc {
     lds = shared;
     Yt = yin + G.off0;
     sv = G.sv;
-    sz = G.sz;
     const int tid = ty * TX + tx;
 #pragma unroll
     for (int m = 0; m < S::SLOTS; ++m) {
@@ -105,14 +106,13 @@ struct LSrc {
       gy = gy < -G.g ? -G.g : (gy > G.n[1] + G.g - 1 ? G.n[1] + G.g - 1 : gy);
       off[m] = gx + gy * G.sy + (k + dz) * G.sz;
     }
-    b0o = (ty + 3) * S::W0 + tx + 3;
-    b1o = S::N0 + (ty + 2) * S::W1 + tx + 2;
+    b0o = ty * S::W0 + tx;
+    b1o = S::N0 + ty * S::W1 + tx;
     b3o = S::N0 + 4 * S::N1 + ty * TX + tx;
     const int ci = x0 + tx < G.n[0] ? x0 + tx : G.n[0] - 1;
     const int cj = y0 + ty < G.n[1] ? y0 + ty : G.n[1] - 1;
     Yc = Yt + ci + (long long)cj * G.sy + (long long)k * G.sz;
     seq = 0;
-    more = false;
   }
 
   __device__ __forceinline__ void prefetch(int v) {
@@ -133,21 +133,9 @@ struct LSrc {
       if (m < S::SLOTS - 1 || t < S::TOTAL) buf[t] = reg[m];
     }
     __syncthreads();
-    if (seq + 1 < V_N) {
-      prefetch(kRhsOrder[seq + 1]);
-    } else if (more) {  // first grid function of the next plane
-#pragma unroll
-      for (int m = 0; m < S::SLOTS; ++m) off[m] += (int)sz;
-      prefetch(kRhsOrder[0]);
-    }
+    if (seq + 1 < V_N) prefetch(kRhsOrder[seq + 1]);
     ++seq;
     return LAcc<TX, TY>{buf + b0o, buf + b1o, buf + b3o};
-  }
-
-  // move to the next plane (after the last acquire of this one)
-  __device__ __forceinline__ void next_plane() {
-    Yc += sz;
-    seq = 0;
   }
 };
 

@@ -396,7 +396,8 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
     for (int q = 0; q < 6; ++q) X[q] = alpha * R[q] - dd[q];
   }
 
-  // ---- At with indices raised by gt^ij
+  // ---- everything that needs the Christoffels, d chi or d alpha is finished
+  // here, so that those die before the shift derivatives are loaded
   T Atm[3][3];  // At^i_j
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -416,6 +417,40 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) AtAt += Atm[i][j] * Atm[j][i];
+
+  const T two3 = (T)2 / (T)3, third = (T)1 / (T)3;
+  const T ichi = (T)1 / chi;
+  // non-advective part of dt Gt^i (also drives B^i), accumulated in Gs
+  T Gs[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T aal = (T)0, ach = (T)0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      aal += Atu[sidx(i, j)] * dalp[j];
+      ach += Atu[sidx(i, j)] * dchi[j];
+    }
+    const T cA = cdu[i][0] * Atu[0] + cdu[i][3] * Atu[3] + cdu[i][5] * Atu[5] +
+                 (T)2 * (cdu[i][1] * Atu[1] + cdu[i][2] * Atu[2] + cdu[i][4] * Atu[4]);
+    Gs[i] = (T)(-2) * aal + (T)2 * alpha * (cA - (T)1.5 * ach * ichi);
+  }
+  // dt K and dt At_ij without their shift and advection terms
+  T rK = -lapalp + alpha * (AtAt + trK * trK * third);
+  T rA[6];
+  {
+    const T trX = gu[0] * X[0] + gu[3] * X[3] + gu[5] * X[5] +
+                  (T)2 * (gu[1] * X[1] + gu[2] * X[2] + gu[4] * X[4]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) {
+        const int q = sidx(i, j);
+        T aa = (T)0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) aa += At[sidx(i, k)] * Atm[k][j];
+        rA[q] = chi * (X[q] - gt[q] * trX * third) + alpha * (trK * At[q] - (T)2 * aa);
+      }
+  }
 
   // ---- shift derivatives: d_j beta^k, gt^jk d_j d_k beta^i, d_j d_k beta^k
   T dbeta[3][3];  // dbeta[k][j] = d_j beta^k
@@ -440,15 +475,42 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
     }
   }
   const T divb = dbeta[0][0] + dbeta[1][1] + dbeta[2][2];
+  rhs[V_CHI] += two3 * chi * (alpha * trK - divb);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const int q = sidx(i, j);
+      T sg = (T)0, sa = (T)0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        sg += gt[sidx(i, k)] * dbeta[k][j] + gt[sidx(j, k)] * dbeta[k][i];
+        sa += At[sidx(i, k)] * dbeta[k][j] + At[sidx(j, k)] * dbeta[k][i];
+      }
+      rhs[V_GT + q] += sg - (T)2 * alpha * At[q] - two3 * gt[q] * divb;
+      rA[q] += sa - two3 * At[q] * divb;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    Gs[i] += -(Gd[0] * dbeta[i][0] + Gd[1] * dbeta[i][1] + Gd[2] * dbeta[i][2]) +
+             two3 * Gd[i] * divb + lapb[i] +
+             third * (gu[sidx(i, 0)] * gdiv[0] + gu[sidx(i, 1)] * gdiv[1] + gu[sidx(i, 2)] * gdiv[2]);
 
   // ---- trK (first derivatives + advection), At and B (advection only)
-  T dK[3];
-  axis_derivs<T, true, false, true>(src.acquire(V_TRK), w, bpos, beta, dK, dpure, adv);
-  rhs[V_TRK] = adv;
+  {
+    T dK[3];
+    axis_derivs<T, true, false, true>(src.acquire(V_TRK), w, bpos, beta, dK, dpure, adv);
+    rhs[V_TRK] = adv + rK;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T gk = gu[sidx(i, 0)] * dK[0] + gu[sidx(i, 1)] * dK[1] + gu[sidx(i, 2)] * dK[2];
+      Gs[i] -= (T)2 * alpha * two3 * gk;
+    }
+  }
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     axis_derivs<T, false, false, true>(src.acquire(V_AT + q), w, bpos, beta, d1v, dpure, adv);
-    rhs[V_AT + q] = adv;
+    rhs[V_AT + q] = adv + rA[q];
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -456,50 +518,13 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
     rhs[V_B + q] = adv;
   }
 
-  // ---- assemble
-  const T two3 = (T)2 / (T)3, third = (T)1 / (T)3;
-  rhs[V_CHI] += two3 * chi * (alpha * trK - divb);
-  rhs[V_TRK] += -lapalp + alpha * (AtAt + trK * trK * third);
-
-  T trX = gu[0] * X[0] + gu[3] * X[3] + gu[5] * X[5] +
-          (T)2 * (gu[1] * X[1] + gu[2] * X[2] + gu[4] * X[4]);
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = i; j < 3; ++j) {
-      const int q = sidx(i, j);
-      T sg = (T)0, sa = (T)0, aa = (T)0;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        sg += gt[sidx(i, k)] * dbeta[k][j] + gt[sidx(j, k)] * dbeta[k][i];
-        sa += At[sidx(i, k)] * dbeta[k][j] + At[sidx(j, k)] * dbeta[k][i];
-        aa += At[sidx(i, k)] * Atm[k][j];
-      }
-      rhs[V_GT + q] += sg - (T)2 * alpha * At[q] - two3 * gt[q] * divb;
-      rhs[V_AT + q] += chi * (X[q] - gt[q] * trX * third) + alpha * (trK * At[q] - (T)2 * aa) +
-                       sa - two3 * At[q] * divb;
-    }
-
-  const T ichi = (T)1 / chi;
+  // ---- gauge
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    T s = -(Gd[0] * dbeta[i][0] + Gd[1] * dbeta[i][1] + Gd[2] * dbeta[i][2]) + two3 * Gd[i] * divb +
-          lapb[i] +
-          third * (gu[sidx(i, 0)] * gdiv[0] + gu[sidx(i, 1)] * gdiv[1] + gu[sidx(i, 2)] * gdiv[2]);
-    T aal = (T)0, ach = (T)0, gk = (T)0, cA = (T)0;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      aal += Atu[sidx(i, j)] * dalp[j];
-      ach += Atu[sidx(i, j)] * dchi[j];
-      gk += gu[sidx(i, j)] * dK[j];
-    }
-    cA = cdu[i][0] * Atu[0] + cdu[i][3] * Atu[3] + cdu[i][5] * Atu[5] +
-         (T)2 * (cdu[i][1] * Atu[1] + cdu[i][2] * Atu[2] + cdu[i][4] * Atu[4]);
-    s += (T)(-2) * aal + (T)2 * alpha * (cA - (T)1.5 * ach * ichi - two3 * gk);
-    rhs[V_GAM + i] += s;
+    rhs[V_GAM + i] += Gs[i];
     if (P.shift == 1) {
       rhs[V_BETA + i] += (T)P.F * (T)src.center(V_B + i);
-      rhs[V_B + i] += s - (T)P.eta * (T)src.center(V_B + i);
+      rhs[V_B + i] += Gs[i] - (T)P.eta * (T)src.center(V_B + i);
     } else {
       rhs[V_BETA + i] = (T)0;
       rhs[V_B + i] = (T)0;
