@@ -101,7 +101,7 @@ int validate_desc(const chemora_grid_desc* d) {
   // element strides of a grid function must fit in 32 bits
   const long long e0 = d->n[0] + 2LL * d->ghost, e1 = d->n[1] + 2LL * d->ghost;
   const long long e2 = d->n[2] + 2LL * d->ghost;
-  const long long sy = ((kAlign + d->n[0] + d->ghost + kAlign - 1) / kAlign) * kAlign;
+  const long long sy = ((kAlign + d->n[0] + d->ghost + 1 + kAlign - 1) / kAlign) * kAlign;
   // one grid function must be addressable with 32-bit element offsets
   if (sy * e1 * e2 > (1LL << 31) - 1 || e0 <= 0)
     return fail(CHEMORA_ERR_INVALID, "grid too large: one grid function exceeds 2^31 elements");
@@ -126,8 +126,9 @@ int chemora_grid_create(const chemora_grid_desc* desc, chemora_grid** out) {
   Geo& G = g->geo;
   for (int a = 0; a < 3; ++a) G.n[a] = desc->n[a];
   G.g = gh;
-  // row: [pad | ghost | interior (starts at column kAlign) | ghost | pad]
-  G.sy = (int)(((kAlign + desc->n[0] + gh + kAlign - 1) / kAlign) * kAlign);
+  // row: [pad | ghost | interior (starts at column kAlign) | ghost | pad >= 1]
+  // (the pad column lets 16-byte copies start at the last ghost column)
+  G.sy = (int)(((kAlign + desc->n[0] + gh + 1 + kAlign - 1) / kAlign) * kAlign);
   G.sz = G.sy * (desc->n[1] + 2 * gh);
   G.sv = (long long)G.sz * (desc->n[2] + 2 * gh);
   G.off0 = kAlign + (long long)gh * G.sy + (long long)gh * G.sz;

@@ -84,6 +84,32 @@ __global__ void __launch_bounds__(TX * TY) bssn_lds_kernel(BssnArgs a) {
                          a.images != 0);
 }
 
+template <int STAGE, typename T, int TX, int TY, int NBUF>
+__global__ void __launch_bounds__(TX * TY) bssn_async_kernel(BssnArgs a) {
+  static_assert(NBUF >= 2 && NBUF <= 6, "1 to 5 grid functions in flight");
+  using S = LdsShape<TX, TY>;
+  // separate arrays, one per buffer (see ASrc); unused ones are not allocated
+  __shared__ double L0[S::TOTAL], L1[S::TOTAL], L2[S::TOTAL], L3[S::TOTAL], L4[S::TOTAL],
+      L5[S::TOTAL];
+  double* const bufs[6] = {L0, L1, L2, L3, L4, L5};
+  const Geo& G = a.G;
+  const int nb = a.tiles[0] * a.tiles[1] * a.tiles[2];
+  const int b = xcd_tile(blockIdx.x, nb);
+  const int bx = b % a.tiles[0], by = (b / a.tiles[0]) % a.tiles[1];
+  const int k = b / (a.tiles[0] * a.tiles[1]);
+  const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
+  const int x0 = bx * TX, y0 = by * TY;
+  const int i = x0 + tx, j = y0 + ty;
+  const bool active = i < G.n[0] && j < G.n[1];
+  ASrc<TX, TY, NBUF> src;
+  src.init(G, a.io.yin, bufs, x0, y0, k, tx, ty);
+  T rhs[V_N];
+  bssn_rhs_point<T>(src, a.W, a.P, rhs);
+  if (active)
+    bssn_store<STAGE, T>(a.io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
+                         a.images != 0);
+}
+
 // CHEMORA_BSSN_TILE=64|32|16 forces the tile width (ablation switch)
 int forced_tile_width() {
   static const int w = [] {
@@ -94,18 +120,29 @@ int forced_tile_width() {
   return w;
 }
 
-bool use_global_kernel() {
-  static const bool g = [] {
+// CHEMORA_BSSN_KERNEL=global|lds|async selects the kernel (ablation switch)
+int kernel_variant() {
+  static const int v = [] {
     const char* e = std::getenv("CHEMORA_BSSN_KERNEL");
-    return e && std::strcmp(e, "global") == 0;
+    if (e && std::strcmp(e, "global") == 0) return 0;
+    if (e && std::strcmp(e, "async") == 0) return 2;
+    return 1;
   }();
-  return g;
+  return v;
 }
+bool use_global_kernel() { return kernel_variant() == 0; }
 
 template <int STAGE, typename T>
 void launch_shape(const BssnArgs& a, dim3 grid, hipStream_t s) {
   if (use_global_kernel()) {
     hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T>), grid, dim3(256), 0, s, a);
+  } else if (kernel_variant() == 2) {
+    if (a.ltx == 64)
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 64, 4, 5>), grid, dim3(256), 0, s, a);
+    else if (a.ltx == 32)
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 32, 8, 6>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 16, 6>), grid, dim3(256), 0, s, a);
   } else if (a.ltx == 64) {
     hipLaunchKernelGGL((bssn_lds_kernel<STAGE, T, 64, 4>), grid, dim3(256), 0, s, a);
   } else if (a.ltx == 32) {

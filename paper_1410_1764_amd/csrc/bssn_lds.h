@@ -140,3 +140,145 @@ struct LSrc {
 };
 
 }  // namespace chemora
+
+namespace chemora {
+
+// ---------------------------------------------------------------------------
+// Asynchronous staging (gfx950 global_load_lds_dwordx4): every lane copies
+// two consecutive doubles straight from global memory into LDS, so the
+// copies of the next D grid functions are in flight while the current one
+// is differentiated, without holding any of them in registers.  Buffers
+// are NBUF = D + 1 separate LDS arrays: the compiler then knows that a read
+// of one buffer does not depend on a copy into another and inserts no wait
+// for it.  The hand-off per grid function is: wait until this wave's copies
+// of it have landed (vmcnt), barrier (all waves' copies landed, and every
+// wave has finished reading the buffer the next copy will overwrite), issue
+// the copy D grid functions ahead into that buffer.  __syncthreads() is not
+// used for it: its fence waits for all outstanding copies.
+//
+// Pairs never straddle a row (every row length is even) and may read one
+// column past the ghost zone, which every row's padding provides.
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef const __attribute__((address_space(1))) void gbl_void_t;
+
+// s_waitcnt vmcnt(n) lgkmcnt(0), expcnt untouched (gfx9 encoding)
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (0 << 8) | (((N >> 4) & 3) << 14));
+}
+
+template <int TX, int TY, int NBUF>
+struct ASrc {
+  using S = LdsShape<TX, TY>;
+  static constexpr int PAIRS = S::TOTAL / 2;
+  static constexpr int PSLOTS = (PAIRS + S::NT - 1) / S::NT;
+  static constexpr int D = NBUF - 1;
+  static_assert(S::TOTAL % 2 == 0 && S::W0 % 2 == 0 && S::W1 % 2 == 0 && TX % 2 == 0,
+                "pairs must not straddle rows");
+  double* buf[NBUF];
+  const char* Yb;        // state allocation (byte address)
+  const double* Yc;      // centre value of variable 0 at the thread's (clamped) point
+  long long sv;          // elements between grid functions
+  unsigned off[PSLOTS];  // byte offset from Yb of each pair slot (variable 0)
+  int b0o, b1o, b3o;
+  int seq;
+  int wbase;             // 64 * wave index
+
+  __device__ __forceinline__ void init(const Geo& G, const double* yin, double* const* shared,
+                                       int x0, int y0, int k, int tx, int ty) {
+#pragma unroll
+    for (int b = 0; b < NBUF; ++b) buf[b] = shared[b];
+    Yb = reinterpret_cast<const char*>(yin);
+    sv = G.sv;
+    const int tid = ty * TX + tx;
+    wbase = tid & ~63;
+#pragma unroll
+    for (int m = 0; m < PSLOTS; ++m) {
+      int p = tid + m * S::NT;
+      if (p >= PAIRS) p = 0;  // masked off at issue
+      const int t = 2 * p;
+      int px, py, dz;
+      if (t < S::N0) {
+        dz = 0;
+        py = t / S::W0 - 3;
+        px = t % S::W0 - 3;
+      } else if (t < S::N0 + 4 * S::N1) {
+        const int r = t - S::N0, s = r / S::N1, q = r % S::N1;
+        dz = (s == 0) ? 1 : (s == 1 ? -1 : (s == 2 ? 2 : -2));
+        py = q / S::W1 - 2;
+        px = q % S::W1 - 2;
+      } else {
+        const int r = t - S::N0 - 4 * S::N1, s = r / S::N3, q = r % S::N3;
+        dz = s == 0 ? 3 : -3;
+        py = q / TX;
+        px = q % TX;
+      }
+      // pair start in [-g-1, n+g-1] keeps both doubles inside the padded row
+      int gx = x0 + px, gy = y0 + py;
+      gx = gx < -G.g - 1 ? -G.g - 1 : (gx > G.n[0] + G.g - 1 ? G.n[0] + G.g - 1 : gx);
+      gy = gy < -G.g ? -G.g : (gy > G.n[1] + G.g - 1 ? G.n[1] + G.g - 1 : gy);
+      off[m] = (unsigned)(8 * (G.off0 + gx + (long long)gy * G.sy + (long long)(k + dz) * G.sz));
+    }
+    b0o = ty * S::W0 + tx;
+    b1o = S::N0 + ty * S::W1 + tx;
+    b3o = S::N0 + 4 * S::N1 + ty * TX + tx;
+    const int ci = x0 + tx < G.n[0] ? x0 + tx : G.n[0] - 1;
+    const int cj = y0 + ty < G.n[1] ? y0 + ty : G.n[1] - 1;
+    Yc = yin + G.off0 + ci + (long long)cj * G.sy + (long long)k * G.sz;
+    seq = 0;
+  }
+
+  // start copying grid function kRhsOrder[s] into buffer s % NBUF
+  __device__ __forceinline__ void issue(int s) {
+    const char* base = Yb + (long long)kRhsOrder[s] * sv * 8;
+    double* dst = buf[s % NBUF];
+    const int lane = (int)threadIdx.x & 63;
+#pragma unroll
+    for (int m = 0; m < PSLOTS; ++m) {
+      if (m < PSLOTS - 1 || wbase + lane + m * S::NT < PAIRS) {
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)(base + off[m]),
+                                         (lds_void_t*)(dst + 2 * (m * S::NT + wbase)), 16, 0, 0);
+      }
+    }
+  }
+
+
+  __device__ __forceinline__ double center(int v) const { return Yc[v * sv]; }
+
+  // copies issued after those of grid function s, counted per wave (full
+  // instructions only: waiting for fewer younger copies is always safe)
+  template <int YOUNGER>
+  __device__ __forceinline__ void wait_and_sync() {
+    wait_vm_lgkm0<YOUNGER * (PSLOTS - 1)>();
+    fence_memory();
+    __builtin_amdgcn_s_barrier();
+    fence_memory();
+  }
+
+  __device__ __forceinline__ LAcc<TX, TY> acquire(int /*v*/) {
+    if (seq == 0) {
+      // prologue: issued after the point's centre loads (kept older by the
+      // fence), so that waiting for a centre value never drains the copies
+      fence_memory();
+#pragma unroll
+      for (int s = 0; s < D; ++s) issue(s);
+    }
+    const int last = seq + D - 1 < V_N - 1 ? seq + D - 1 : V_N - 1;
+    switch (last - seq) {  // folds to one case once seq is known
+      case 0: wait_and_sync<0>(); break;
+      case 1: wait_and_sync<1>(); break;
+      case 2: wait_and_sync<2>(); break;
+      case 3: wait_and_sync<3>(); break;
+      case 4: wait_and_sync<4>(); break;
+      default: wait_and_sync<5>(); break;
+    }
+    if (seq + D < V_N) issue(seq + D);
+    double* b = buf[seq % NBUF];
+    ++seq;
+    return LAcc<TX, TY>{b + b0o, b + b1o, b + b3o};
+  }
+};
+
+}  // namespace chemora
