@@ -115,7 +115,13 @@ def main(argv=None) -> int:
     k64 = _events_time(lambda: g64.rhs(st, rhs), reps)
     kghost = _events_time(lambda: g64.fill_ghosts(st), reps)
     if args.only_rhs:
-        print(json.dumps({"rhs_fp64_ms": k64 * 1e3}))
+        # plus a streaming copy of known size: the calibration kernel for
+        # hardware byte counters collected on this same command
+        nb = 1 << 29
+        a = torch.empty(nb // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        kc = _events_time(lambda: C.probe_copy(b, a, nb), 2)
+        print(json.dumps({"rhs_fp64_ms": k64 * 1e3, "copy_512MiB_ms": kc * 1e3}))
         return 0
 
     for _ in range(args.warmup):

@@ -12,6 +12,8 @@ marshals numpy arrays in the oracle's own unpadded layout
 What each routine follows in the paper (arXiv:1410.1764):
   * ``wave_rhs``: eq. (1), two-variable reading (du/dt = rho, drho/dt = Lap u),
     4th-order centred differences (Sec. III.B.2, Discretisation description).
+  * ``wave5_rhs`` / ``wave5_energy``: eq. (1) in the paper's own first-order
+    five-variable form and Fig. 1's Energy calculation.
   * ``bssn_rhs``: the Einstein equations in BSSN form that Sec. III.D evolves
     (chi variant; 1+log or harmonic slicing; Gamma-driver or frozen shift;
     lopsided stencils for advection).
@@ -42,9 +44,9 @@ LIB = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c11",
           "-Wall", "-shared", "-fPIC"]
 
-WAVE, BSSN = 1, 2
+WAVE, BSSN, WAVE5 = 1, 2, 3
 BC_PERIODIC, BC_GAUGEWAVE = 0, 1
-NVAR = {WAVE: 2, BSSN: 24}
+NVAR = {WAVE: 2, BSSN: 24, WAVE5: 5}
 
 
 def build() -> str:
@@ -81,6 +83,9 @@ def _load():
     lib.orc_fill_gaugewave.argtypes = [P, ctypes.c_double, _DP]
     lib.orc_wave_rhs.argtypes = [P, _DP, _DP]
     lib.orc_bssn_rhs.argtypes = [P, _DP, _DP]
+    lib.orc_wave5_rhs.argtypes = [P, _DP, _DP]
+    lib.orc_wave5_energy.argtypes = [P, _DP, _DP]
+    lib.orc_wave5_energy.restype = ctypes.c_double
     lib.orc_rk4.argtypes = [P, ctypes.c_int, ctypes.c_int, _DP, ctypes.c_double,
                             ctypes.c_double, ctypes.c_int]
     lib.orc_rk4.restype = ctypes.c_int
@@ -165,6 +170,20 @@ def wave_rhs(b: Block, y: np.ndarray) -> np.ndarray:
     r = np.zeros_like(y)
     _load().orc_wave_rhs(ctypes.byref(b._p), _ptr(y), _ptr(r))
     return r
+
+
+def wave5_rhs(b: Block, y: np.ndarray) -> np.ndarray:
+    assert y.shape[0] == 5
+    r = np.zeros_like(y)
+    _load().orc_wave5_rhs(ctypes.byref(b._p), _ptr(y), _ptr(r))
+    return r
+
+
+def wave5_energy(b: Block, y: np.ndarray, want_field: bool = False):
+    """(total energy, eps field or None): Fig. 1's Energy calculation"""
+    eps = b.zeros(1) if want_field else None
+    e = _load().orc_wave5_energy(ctypes.byref(b._p), _ptr(y), _ptr(eps))
+    return e, eps
 
 
 def bssn_rhs(b: Block, y: np.ndarray) -> np.ndarray:

@@ -12,7 +12,10 @@
  *     "Discretisation description": standard centred finite-difference
  *     operators, here of 4th order);
  *   - the scalar wave system in the two-variable reading du/dt = rho,
- *     drho/dt = Laplacian(u) (eq. (1) with v_i = d_i u eliminated);
+ *     drho/dt = Laplacian(u) (eq. (1) with v_i = d_i u eliminated), and in
+ *     the paper's own first-order form with five variables (eq. (1),
+ *     Fig. 1: du/dt = rho, drho/dt = d_i v_i, dv_i/dt = d_i rho) with the
+ *     energy density eps = (rho^2 + v_i v_i)/2 of Fig. 1's Energy calculation;
  *   - the BSSN form of the Einstein equations that the paper evolves
  *     (Sec. III.D "Single-node performance"; its cited formulation), in the
  *     chi-variant with 1+log or harmonic slicing and a Gamma-driver or
@@ -192,11 +195,15 @@ void orc_fill_gaugewave(const orc_params* p, double t, double* y) {
       }
 }
 
+static int nvars_of(int system) {
+  return system == ORC_WAVE ? 2 : (system == ORC_WAVE5 ? 5 : NB);
+}
+
 static void fill_ghosts(const orc_params* p, int system, int bc, double t, double* y) {
   if (system == ORC_BSSN && bc == ORC_BC_GAUGEWAVE)
     orc_fill_gaugewave(p, t, y);
   else
-    orc_fill_periodic(p, system == ORC_WAVE ? 2 : NB, y);
+    orc_fill_periodic(p, nvars_of(system), y);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -217,6 +224,51 @@ void orc_wave_rhs(const orc_params* p, const double* y, double* r) {
         r[G.npts + q] = fd2(u + q, st[0], p->h[0]) + fd2(u + q, st[1], p->h[1]) +
                         fd2(u + q, st[2], p->h[2]);
       }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scalar wave, eq. (1) in the paper's first-order form (Fig. 1 "RHS"):
+ *   du/dt = rho,  drho/dt = d_x v_1 + d_y v_2 + d_z v_3,  dv_i/dt = d_i rho
+ * with the 4th-order centred first derivative.                              */
+
+void orc_wave5_rhs(const orc_params* p, const double* y, double* r) {
+  geom G = mkgeom(p);
+  const long st[3] = {1, G.sy, G.sz};
+  const double* rho = y + G.npts;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < G.n[2]; k++)
+    for (int j = 0; j < G.n[1]; j++)
+      for (int i = 0; i < G.n[0]; i++) {
+        const long q = idx(&G, i, j, k);
+        r[q] = rho[q];
+        double div = 0.0;
+        for (int a = 0; a < 3; a++) div += fd1(y + (2 + a) * G.npts + q, st[a], p->h[a]);
+        r[G.npts + q] = div;
+        for (int a = 0; a < 3; a++) r[(2 + a) * G.npts + q] = fd1(rho + q, st[a], p->h[a]);
+      }
+}
+
+/* Fig. 1 "Energy": eps = (rho^2 + v_i v_i)/2 at interior points (eps may be
+ * NULL); returns the total sum(eps) h_x h_y h_z, summed plane by plane. */
+double orc_wave5_energy(const orc_params* p, const double* y, double* eps) {
+  geom G = mkgeom(p);
+  const int nz = G.n[2];
+  double* plane = calloc((size_t)nz, sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < nz; k++)
+    for (int j = 0; j < G.n[1]; j++)
+      for (int i = 0; i < G.n[0]; i++) {
+        const long q = idx(&G, i, j, k);
+        const double rho = y[G.npts + q], v1 = y[2 * G.npts + q], v2 = y[3 * G.npts + q],
+                     v3 = y[4 * G.npts + q];
+        const double e = 0.5 * (rho * rho + (v1 * v1 + v2 * v2 + v3 * v3));
+        if (eps) eps[q] = e;
+        plane[k] += e;
+      }
+  double s = 0.0;
+  for (int k = 0; k < nz; k++) s += plane[k];
+  free(plane);
+  return s * p->h[0] * p->h[1] * p->h[2];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -538,6 +590,8 @@ void orc_bssn_constraints(const orc_params* p, const double* y, double* hm,
 static void rhs(const orc_params* p, int system, const double* y, double* r) {
   if (system == ORC_WAVE)
     orc_wave_rhs(p, y, r);
+  else if (system == ORC_WAVE5)
+    orc_wave5_rhs(p, y, r);
   else
     orc_bssn_rhs(p, y, r);
 }
@@ -560,7 +614,7 @@ static void axpy_interior(const geom* G, int nvar, const double* y, double c,
 int orc_rk4(const orc_params* p, int system, int bc, double* y, double t, double dt,
             int nsteps) {
   geom G = mkgeom(p);
-  const int nvar = (system == ORC_WAVE) ? 2 : NB;
+  const int nvar = nvars_of(system);
   const size_t N = (size_t)nvar * G.npts;
   double* ys = calloc(N, sizeof(double));
   double* k1 = calloc(N, sizeof(double));

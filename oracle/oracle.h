@@ -16,6 +16,7 @@
  * order listed below.
  *
  * Wave system (2 variables): u, rho.
+ * First-order wave system (5 variables): u, rho, v1, v2, v3.
  * BSSN system (24 variables): chi, gt11, gt12, gt13, gt22, gt23, gt33, trK,
  *   At11, At12, At13, At22, At23, At33, Gamt1, Gamt2, Gamt3, alpha,
  *   beta1, beta2, beta3, B1, B2, B3.
@@ -37,13 +38,15 @@ typedef struct {
   int gw_axis;         /* gauge wave direction 0,1,2 */
 } orc_params;
 
-enum { ORC_WAVE = 1, ORC_BSSN = 2 };
+enum { ORC_WAVE = 1, ORC_BSSN = 2, ORC_WAVE5 = 3 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_GAUGEWAVE = 1 };
 
 int  orc_num_threads(void);
 void orc_fill_periodic(const orc_params* p, int nvar, double* f);
 void orc_fill_gaugewave(const orc_params* p, double t, double* y);
 void orc_wave_rhs(const orc_params* p, const double* y, double* r);
+void orc_wave5_rhs(const orc_params* p, const double* y, double* r);
+double orc_wave5_energy(const orc_params* p, const double* y, double* eps);
 void orc_bssn_rhs(const orc_params* p, const double* y, double* r);
 int  orc_rk4(const orc_params* p, int system, int bc, double* y, double t,
              double dt, int nsteps);

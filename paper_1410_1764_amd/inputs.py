@@ -25,6 +25,7 @@ BSSN_NAMES = ["chi", "gt11", "gt12", "gt13", "gt22", "gt23", "gt33", "trK",
               "At11", "At12", "At13", "At22", "At23", "At33", "Gamt1", "Gamt2",
               "Gamt3", "alpha", "beta1", "beta2", "beta3", "B1", "B2", "B3"]
 WAVE_NAMES = ["u", "rho"]
+WAVE5_NAMES = ["u", "rho", "v1", "v2", "v3"]
 
 
 def _ntuple(n):
@@ -73,6 +74,42 @@ def travelling_mode(n, kvec, t: float = 0.0) -> np.ndarray:
     w = 2 * np.pi * np.sqrt((k ** 2).sum())
     ph = 2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) - w * t
     return np.stack([np.sin(ph), -w * np.cos(ph)])
+
+
+def gaussian_pulse(n, A: float = 1.0, W: float = 0.08, centre=(0.5, 0.5, 0.5)) -> np.ndarray:
+    """Fig. 1's Init calculation for the first-order wave system:
+    u = 0, rho = A exp(-(r/W)^2 / 2) with r the distance to `centre`, v_i = 0,
+    on the unit cube with x_i = i/n."""
+    nn = _ntuple(n)
+    X = _grid(nn, tuple(1.0 / v for v in nn), (0.0, 0.0, 0.0))
+    r2 = sum((X[d] - centre[d]) ** 2 for d in range(3))
+    y = np.zeros((5, nn[2], nn[1], nn[0]))
+    y[1] = A * np.exp(-0.5 * r2 / W ** 2)
+    return y
+
+
+def wave5_plane(n, kvec, t: float = 0.0) -> np.ndarray:
+    """Exact plane wave of the first-order system: u = sin(theta),
+    theta = 2 pi k.x - w t, w = 2 pi |k|; rho = du/dt, v_i = d_i u."""
+    nn = _ntuple(n)
+    X = _grid(nn, tuple(1.0 / v for v in nn), (0.0, 0.0, 0.0))
+    k = np.asarray(kvec, dtype=float)
+    w = 2 * np.pi * np.sqrt((k ** 2).sum())
+    th = 2 * np.pi * (k[0] * X[0] + k[1] * X[1] + k[2] * X[2]) - w * t
+    y = np.zeros((5, nn[2], nn[1], nn[0]))
+    y[0] = np.sin(th)
+    y[1] = -w * np.cos(th)
+    for d in range(3):
+        y[2 + d] = 2 * np.pi * k[d] * np.cos(th)
+    return y
+
+
+def wave5_fourier(n: int, K: int, seed: int) -> np.ndarray:
+    """five independent seeded Fourier-mode fields (|k| <= K), one per variable"""
+    y = np.zeros((5, n, n, n))
+    for v in range(5):
+        y[v] = fourier_modes(n, K, seed + 97 * v)[0]
+    return y
 
 
 # ----------------------------------------------------------------------------
