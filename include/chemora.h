@@ -36,6 +36,7 @@
  * stride sv.  Every value is an IEEE double (FP64) in memory, in both
  * precision modes.  Variable order:
  *   wave (2):  u, rho
+ *   wave5 (5): u, rho, v1, v2, v3
  *   BSSN (24): chi, gt11, gt12, gt13, gt22, gt23, gt33, trK, At11, At12,
  *              At13, At22, At23, At33, Gamt1, Gamt2, Gamt3, alpha, beta1,
  *              beta2, beta3, B1, B2, B3
@@ -70,7 +71,10 @@ typedef enum {
   CHEMORA_ERR_HOST_NOMEM = 4   /* host allocation failed */
 } chemora_status;
 
-enum { CHEMORA_WAVE = 1, CHEMORA_BSSN = 2 };
+/* WAVE: eq. (1) in the two-variable reading (du/dt = rho, drho/dt = Lap u);
+ * BSSN: the Einstein equations (Sec. III.D); WAVE5: eq. (1) in the paper's
+ * own first-order form (Fig. 1: u, rho, v_i). */
+enum { CHEMORA_WAVE = 1, CHEMORA_BSSN = 2, CHEMORA_WAVE5 = 3 };
 /* FP64: all arithmetic in double.  MIXED: differences of neighbouring
  * values in double, then stencil weights and the right-hand-side algebra in
  * float; state, RK4 accumulation and constraints stay double. */
@@ -85,10 +89,10 @@ enum { CHEMORA_SHIFT_FROZEN = 0, CHEMORA_SHIFT_GAMMADRIVER = 1 };
  * run-time parameters of the physics system). */
 typedef struct {
   int32_t n[3];      /* interior points per axis, each >= 1 */
-  int32_t ghost;     /* ghost width: >= 2 for the wave, >= 3 for BSSN, <= 8 */
+  int32_t ghost;     /* ghost width: >= 2 for the wave systems, >= 3 for BSSN, <= 8 */
   double h[3];       /* spacing per axis, > 0 */
   double origin[3];  /* coordinate of interior point (0,0,0) */
-  int32_t system;    /* CHEMORA_WAVE or CHEMORA_BSSN */
+  int32_t system;    /* CHEMORA_WAVE, CHEMORA_BSSN or CHEMORA_WAVE5 */
   int32_t precision; /* CHEMORA_FP64 or CHEMORA_MIXED */
   int32_t boundary;  /* CHEMORA_BC_*; periodic needs n >= ghost per axis */
   int32_t slicing;   /* BSSN: 1+log (dt alpha = adv - 2 alpha K) or harmonic (- alpha^2 K) */
@@ -156,6 +160,16 @@ int chemora_rk4_step(chemora_grid* grid, double* state, void* workspace, double 
 int64_t chemora_constraints_workspace_bytes(const chemora_grid* grid);
 int chemora_constraints(chemora_grid* grid, const double* state, double* hm, double* norms,
                         void* workspace, chemora_stream stream);
+
+/* Fig. 1's "Energy" calculation for the first-order wave system (WAVE5):
+ * eps = (rho^2 + v_i v_i)/2 at interior points, written to eps (a 1-variable
+ * state, may be NULL), and the total sum(eps) h_x h_y h_z written to the
+ * device double *total, summed in a fixed order (bitwise reproducible).
+ * workspace: chemora_energy_workspace_bytes(grid) bytes.  Other systems:
+ * CHEMORA_ERR_UNSUPPORTED. */
+int64_t chemora_energy_workspace_bytes(const chemora_grid* grid);
+int chemora_energy(chemora_grid* grid, const double* state, double* eps, double* total,
+                   void* workspace, chemora_stream stream);
 
 /* ---- batches of uneven patches (Sec. IV: mesh-refinement / multi-block
  * patches of the Carpet driver; Sec. III.B.3: a GPU run-time library that

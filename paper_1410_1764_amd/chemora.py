@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libchemora.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "chemora.h")
 
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_DEVICE, ERR_HOST_NOMEM = 0, 1, 2, 3, 4
-WAVE, BSSN = 1, 2
+WAVE, BSSN, WAVE5 = 1, 2, 3
 FP64, MIXED = 0, 1
 BC_PERIODIC, BC_GAUGEWAVE, BC_CALLER = 0, 1, 2
 SLICING_1PLUSLOG, SLICING_HARMONIC = 0, 1
@@ -71,6 +71,8 @@ def lib():
         "chemora_rk4_step": (ctypes.c_int, [_vp, _vp, _vp, dbl, dbl, i32, _vp]),
         "chemora_constraints_workspace_bytes": (i64, [_vp]),
         "chemora_constraints": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "chemora_energy_workspace_bytes": (i64, [_vp]),
+        "chemora_energy": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "chemora_batch_meta_bytes": (i64, [i32]),
         "chemora_batch_step": (ctypes.c_int, [ctypes.POINTER(Patch), i32, _vp, dbl, dbl, i32,
                                               _vp]),
@@ -221,6 +223,19 @@ class Grid:
         check(lib().chemora_constraints(self.handle, _ptr(state), _ptr(hm), _ptr(norms),
                                         _ptr(workspace), _stream(stream)))
         return norms
+
+
+    def energy(self, state, eps=None, total=None, workspace=None, stream=None):
+        """Fig. 1's Energy calculation (WAVE5): total = sum(eps) h^3 (device)"""
+        import torch
+        if total is None:
+            total = torch.zeros(1, dtype=torch.float64, device=state.device)
+        if workspace is None:
+            nb = lib().chemora_energy_workspace_bytes(self.handle)
+            workspace = torch.empty(max(nb // 8, 1), dtype=torch.float64, device=state.device)
+        check(lib().chemora_energy(self.handle, _ptr(state), _ptr(eps), _ptr(total),
+                                   _ptr(workspace), _stream(stream)))
+        return total
 
 
 def probe_copy(dst, src, nbytes: int, stream=None):

@@ -54,10 +54,11 @@ namespace {
 
 int validate_desc(const chemora_grid_desc* d) {
   if (!d) return fail(CHEMORA_ERR_INVALID, "grid description is NULL");
-  if (d->system != CHEMORA_WAVE && d->system != CHEMORA_BSSN)
-    return fail(CHEMORA_ERR_INVALID, "system must be CHEMORA_WAVE (1) or CHEMORA_BSSN (2), got %d",
+  if (d->system != CHEMORA_WAVE && d->system != CHEMORA_BSSN && d->system != CHEMORA_WAVE5)
+    return fail(CHEMORA_ERR_INVALID,
+                "system must be CHEMORA_WAVE (1), CHEMORA_BSSN (2) or CHEMORA_WAVE5 (3), got %d",
                 d->system);
-  const int gmin = d->system == CHEMORA_WAVE ? 2 : 3;
+  const int gmin = d->system == CHEMORA_BSSN ? 3 : 2;
   if (d->ghost < gmin || d->ghost > kMaxGhost)
     return fail(CHEMORA_ERR_INVALID, "ghost must be in [%d, %d] for this system, got %d", gmin,
                 kMaxGhost, d->ghost);
@@ -132,7 +133,7 @@ int chemora_grid_create(const chemora_grid_desc* desc, chemora_grid** out) {
   G.sz = G.sy * (desc->n[1] + 2 * gh);
   G.sv = (long long)G.sz * (desc->n[2] + 2 * gh);
   G.off0 = kAlign + (long long)gh * G.sy + (long long)gh * G.sz;
-  g->nvars = desc->system == CHEMORA_WAVE ? 2 : 24;
+  g->nvars = desc->system == CHEMORA_WAVE ? 2 : (desc->system == CHEMORA_WAVE5 ? 5 : 24);
   g->state_elems = G.sv * g->nvars;
   BssnPar& P = g->par;
   for (int a = 0; a < 3; ++a) {
@@ -200,6 +201,8 @@ static hipError_t launch_stage(const chemora_grid* g, int stage, bool images, co
                                hipStream_t s) {
   if (g->d.system == CHEMORA_WAVE)
     return launch_wave_stage(g->geo, g->d.h, stage, g->d.precision, images, io, s);
+  if (g->d.system == CHEMORA_WAVE5)
+    return launch_wave5_stage(g->geo, g->d.h, stage, g->d.precision, images, io, s);
   return launch_bssn_stage(g->geo, g->par, stage, g->d.precision, images, io, s);
 }
 
@@ -284,6 +287,30 @@ int chemora_constraints(chemora_grid* grid, const double* state, double* hm, dou
                                                static_cast<double*>(workspace),
                                                static_cast<hipStream_t>(stream)),
                        "constraints launch");
+}
+
+int64_t chemora_energy_workspace_bytes(const chemora_grid* grid) {
+  if (!grid) {
+    fail(CHEMORA_ERR_INVALID, "grid is NULL");
+    return -1;
+  }
+  return energy_partial_count(grid->geo) * (int64_t)sizeof(double);
+}
+
+int chemora_energy(chemora_grid* grid, const double* state, double* eps, double* total,
+                   void* workspace, chemora_stream stream) {
+  if (!grid) return fail(CHEMORA_ERR_INVALID, "grid is NULL");
+  if (grid->d.system != CHEMORA_WAVE5)
+    return fail(CHEMORA_ERR_UNSUPPORTED, "the energy calculation exists for CHEMORA_WAVE5 only");
+  if (!state || !total || !workspace)
+    return fail(CHEMORA_ERR_INVALID, "state, total and workspace must not be NULL");
+  if (!aligned(state) || !aligned(workspace) || (eps && !aligned(eps)) ||
+      (reinterpret_cast<uintptr_t>(total) & 7u))
+    return fail(CHEMORA_ERR_INVALID, "misaligned pointer");
+  return device_status(launch_wave5_energy(grid->geo, grid->d.h, state, eps, total,
+                                           static_cast<double*>(workspace),
+                                           static_cast<hipStream_t>(stream)),
+                       "energy launch");
 }
 
 int chemora_probe_copy(void* dst, const void* src, int64_t nbytes, chemora_stream stream) {

@@ -85,6 +85,11 @@ hipError_t launch_fill_gaugewave(const Geo& G, const BssnPar& P, double t, doubl
                                  hipStream_t s);
 hipError_t launch_wave_stage(const Geo& G, const double h[3], int stage, int precision,
                              bool images, const StageIO& io, hipStream_t s);
+hipError_t launch_wave5_stage(const Geo& G, const double h[3], int stage, int precision,
+                              bool images, const StageIO& io, hipStream_t s);
+long long energy_partial_count(const Geo& G);
+hipError_t launch_wave5_energy(const Geo& G, const double h[3], const double* y, double* eps,
+                               double* total, double* partial, hipStream_t s);
 hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int precision,
                              bool images, const StageIO& io, hipStream_t s);
 hipError_t launch_bssn_constraints(const Geo& G, const BssnPar& P, const double* y,
