@@ -120,23 +120,32 @@ int forced_tile_width() {
   return w;
 }
 
-// CHEMORA_BSSN_KERNEL=global|lds|async selects the kernel (ablation switch)
-int kernel_variant() {
+// Kernel choice (measured at 128^3): FP64 -> async staging (five grid
+// functions in flight hide the memory latency that one wave per SIMD
+// cannot); mixed -> LDS staging (its 248 VGPRs and 44 KB of LDS allow two
+// waves per SIMD).  CHEMORA_BSSN_KERNEL=global|lds|async overrides it
+// (ablation switch).
+int kernel_override() {
   static const int v = [] {
     const char* e = std::getenv("CHEMORA_BSSN_KERNEL");
     if (e && std::strcmp(e, "global") == 0) return 0;
+    if (e && std::strcmp(e, "lds") == 0) return 1;
     if (e && std::strcmp(e, "async") == 0) return 2;
-    return 1;
+    return -1;
   }();
   return v;
 }
-bool use_global_kernel() { return kernel_variant() == 0; }
+int kernel_variant(int precision) {
+  const int o = kernel_override();
+  return o >= 0 ? o : (precision == CHEMORA_MIXED ? 1 : 2);
+}
 
 template <int STAGE, typename T>
 void launch_shape(const BssnArgs& a, dim3 grid, hipStream_t s) {
-  if (use_global_kernel()) {
+  const int variant = kernel_variant(sizeof(T) == 4 ? CHEMORA_MIXED : CHEMORA_FP64);
+  if (variant == 0) {
     hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T>), grid, dim3(256), 0, s, a);
-  } else if (kernel_variant() == 2) {
+  } else if (variant == 2) {
     if (a.ltx == 64)
       hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 64, 4, 5>), grid, dim3(256), 0, s, a);
     else if (a.ltx == 32)
@@ -174,7 +183,7 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
   a.W = make_weights(P.h);
   a.io = io;
   a.images = images ? 1 : 0;
-  a.ltx = G.n[0] >= 48 ? 64 : (G.n[0] >= 24 ? 32 : 16);
+  a.ltx = G.n[0] >= 24 ? 32 : 16;
   if (forced_tile_width()) a.ltx = forced_tile_width();
   a.lty = 256 / a.ltx;
   a.tiles[0] = (G.n[0] + a.ltx - 1) / a.ltx;
@@ -182,7 +191,7 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
   const long long xy = (long long)a.tiles[0] * a.tiles[1];
   // global kernel: enough workgroups for several rounds per CU, each
   // marching zc planes; LDS kernel: one plane per workgroup
-  const long long want = use_global_kernel() ? 8192 : (long long)1 << 40;
+  const long long want = kernel_variant(precision) == 0 ? 8192 : (long long)1 << 40;
   int zsplit = (int)std::min<long long>((want + xy - 1) / xy, G.n[2]);
   if (zsplit > G.n[2]) zsplit = G.n[2];
   if (zsplit < 1) zsplit = 1;
