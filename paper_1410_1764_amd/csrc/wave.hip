@@ -87,13 +87,15 @@ __global__ void __launch_bounds__(TX * TY) wave_stage_kernel(WaveArgs a) {
       } else {
         double* acc = a.io.acc + G.off0;
         const double* y0 = a.io.y0 + G.off0;
-        double u0, r0;
+        double u0, r0, au = 0.0, ar = 0.0;
         if (STAGE == 1) {
           u0 = c;
           r0 = rho;
         } else {
           u0 = y0[p];
           r0 = y0[p + G.sv];
+          au = acc[p];  // loads before the first store
+          ar = acc[p + G.sv];
         }
         double nu, nr;
         if (STAGE == 1) {
@@ -102,13 +104,13 @@ __global__ void __launch_bounds__(TX * TY) wave_stage_kernel(WaveArgs a) {
           nu = u0 + a.io.cdt * ku;
           nr = r0 + a.io.cdt * kr;
         } else if (STAGE == 2 || STAGE == 3) {
-          acc[p] = acc[p] + 2.0 * ku;
-          acc[p + G.sv] = acc[p + G.sv] + 2.0 * kr;
+          acc[p] = au + 2.0 * ku;
+          acc[p + G.sv] = ar + 2.0 * kr;
           nu = u0 + a.io.cdt * ku;
           nr = r0 + a.io.cdt * kr;
         } else {
-          nu = u0 + a.io.cdt * (acc[p] + ku);
-          nr = r0 + a.io.cdt * (acc[p + G.sv] + kr);
+          nu = u0 + a.io.cdt * (au + ku);
+          nr = r0 + a.io.cdt * (ar + kr);
         }
         store_with_images(out, G, i, j, k, nu, a.images);
         store_with_images(out + G.sv, G, i, j, k, nr, a.images);

@@ -62,25 +62,32 @@ __global__ void __launch_bounds__(TX * TY) wave5_stage_kernel(W5Args a) {
                   d1(w0, w1, w3, w4, cz);
     const double kv[5] = {r2, (double)div, (double)drx, (double)dry, (double)drz};
     double* out = a.io.out + G.off0;
+    if (STAGE == 0) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const long long q = p + v * sv;
-      if (STAGE == 0) {
-        out[q] = kv[v];
-        continue;
+      for (int v = 0; v < 5; ++v) out[p + v * sv] = kv[v];
+    } else {
+      // every pointwise load before the first store (see bssn_store)
+      double y0[5], ac[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        y0[v] = STAGE == 1 ? Y[p + v * sv] : a.io.y0[G.off0 + p + v * sv];
+        ac[v] = STAGE == 1 ? 0.0 : a.io.acc[G.off0 + p + v * sv];
       }
-      const double y0 = STAGE == 1 ? Y[q] : a.io.y0[G.off0 + q];
-      double nv;
-      if (STAGE == 1) {
-        a.io.acc[G.off0 + q] = kv[v];
-        nv = y0 + a.io.cdt * kv[v];
-      } else if (STAGE == 2 || STAGE == 3) {
-        a.io.acc[G.off0 + q] = a.io.acc[G.off0 + q] + 2.0 * kv[v];
-        nv = y0 + a.io.cdt * kv[v];
-      } else {
-        nv = y0 + a.io.cdt * (a.io.acc[G.off0 + q] + kv[v]);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const long long q = p + v * sv;
+        double nv;
+        if (STAGE == 1) {
+          a.io.acc[G.off0 + q] = kv[v];
+          nv = y0[v] + a.io.cdt * kv[v];
+        } else if (STAGE == 2 || STAGE == 3) {
+          a.io.acc[G.off0 + q] = ac[v] + 2.0 * kv[v];
+          nv = y0[v] + a.io.cdt * kv[v];
+        } else {
+          nv = y0[v] + a.io.cdt * (ac[v] + kv[v]);
+        }
+        store_with_images(out + v * sv, G, i, j, k, nv, a.images != 0);
       }
-      store_with_images(out + v * sv, G, i, j, k, nv, a.images != 0);
     }
     r0 = r1;
     r1 = r2;
