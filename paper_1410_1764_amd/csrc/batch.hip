@@ -14,6 +14,13 @@
 // ordering.  Workgroups take items round-robin (item = wg + r * grid), in an
 // order sorted by decreasing cost (longest-processing-time first).
 //
+// Three kernel kinds share this structure: kind 0 reads stencil neighbours
+// through the caches with a tile shape per patch (size class); kinds 1 and 2
+// stage each grid function's tile neighbourhood in LDS (bssn_lds.h: async
+// copies in FP64, register-prefetched LDS in mixed precision) with 32x8 or
+// 16x16 single-plane tiles.  The autotuner picks the kind and, for kind 0,
+// the tile of each size class.
+//
 // The four substage launches and a one-thread clock update (t += dt) are
 // captured once into a HIP graph and replayed per step; the time lives in a
 // device scalar so the frozen kernel arguments stay valid.
@@ -27,7 +34,10 @@
 #include <string>
 #include <vector>
 
-#include "bssn_point.h"
+#include <cstdlib>
+#include <type_traits>
+
+#include "bssn_lds.h"
 
 namespace chemora {
 
@@ -171,13 +181,54 @@ __device__ __forceinline__ void stage_buffers(const PatchDesc& p, int io, StageI
   }
 }
 
-template <int STAGE, typename T>
+template <int KIND>
+struct KindShape {
+  static constexpr int TX = KIND == 2 ? 16 : 32, TY = KIND == 2 ? 16 : 8;
+  static constexpr int TOT = KIND == 0 ? 1 : LdsShape<TX, TY>::TOTAL;
+};
+
+// one single-plane tile of a staged kind
+template <int STAGE, typename T, int KIND>
+__device__ __forceinline__ void staged_tile(const PatchDesc& p, const StageIO& io, long long tile,
+                                            double* const* bufs) {
+  constexpr int TX = KindShape<KIND>::TX, TY = KindShape<KIND>::TY;
+  const Geo& G = p.G;
+  const int bx = (int)(tile % p.tiles[0]);
+  const int by = (int)((tile / p.tiles[0]) % p.tiles[1]);
+  const int k = (int)(tile / ((long long)p.tiles[0] * p.tiles[1]));
+  const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
+  const int x0 = bx * TX, y0 = by * TY;
+  const int i = x0 + tx, j = y0 + ty;
+  T rhs[V_N];
+  if constexpr (std::is_same<T, double>::value) {
+    ASrc<TX, TY, 6> src;
+    src.init(G, io.yin, bufs, x0, y0, k, tx, ty);
+    bssn_rhs_point<T>(src, p.W, p.P, rhs);
+  } else {
+    LSrc<TX, TY> src;
+    src.init(G, io.yin, bufs[0], bufs[1], x0, y0, k, tx, ty);
+    src.prefetch(kRhsOrder[0]);
+    bssn_rhs_point<T>(src, p.W, p.P, rhs);
+  }
+  if (i < G.n[0] && j < G.n[1])
+    bssn_store<STAGE, T>(io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
+                         false);
+}
+
+template <int STAGE, typename T, int KIND>
 __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
   __shared__ int s_patch;
+  constexpr int TOT = KindShape<KIND>::TOT;
+  constexpr int NB = KIND == 0 ? 0 : (std::is_same<T, double>::value ? 6 : 2);
+  // separate arrays, one per staging buffer (see bssn_lds.h); only the ones
+  // referenced by this kind and precision are allocated
+  __shared__ double L0[TOT], L1[TOT], L2[TOT], L3[TOT], L4[TOT], L5[TOT];
+  double* bufs[6] = {L0, L1, NB > 2 ? L2 : nullptr, NB > 2 ? L3 : nullptr,
+                     NB > 2 ? L4 : nullptr, NB > 2 ? L5 : nullptr};
   const double tnow = *B.clock;
   for (long long item = blockIdx.x; item < B.n_total; item += gridDim.x) {
     const bool interior = item < B.n_interior;
-    __syncthreads();  // s_patch of the previous item has been read by all
+    __syncthreads();  // the previous item is finished by every wave
     if (threadIdx.x == 0)
       s_patch = interior ? find_patch(B.prefix, B.np, item)
                          : find_patch(B.gprefix, B.np, item - B.n_interior);
@@ -188,19 +239,23 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
     stage_buffers(p, B.stage_io, io, B.dt);
     if (interior) {
       const long long tile = item - B.prefix[s_patch];
-      const int tx = (int)(tile % p.tiles[0]);
-      const int ty = (int)((tile / p.tiles[0]) % p.tiles[1]);
-      const int tzi = (int)(tile / ((long long)p.tiles[0] * p.tiles[1]));
-      const int lx = (int)threadIdx.x % p.ltx, ly = (int)threadIdx.x / p.ltx;
-      const int i = tx * p.ltx + lx, j = ty * p.lty + ly;
-      if (ly < p.lty && i < G.n[0] && j < G.n[1]) {
-        const int k0 = tzi * p.tz, k1 = min(k0 + p.tz, G.n[2]);
-        for (int k = k0; k < k1; ++k) {
-          const long long q = i + (long long)j * G.sy + (long long)k * G.sz;
-          T rhs[V_N];
-          GSrc src{io.yin + G.off0 + q, G.sv, G.sy, G.sz};
-          bssn_rhs_point<T>(src, p.W, p.P, rhs);
-          bssn_store<STAGE, T>(io, G, q, i, j, k, rhs, false);
+      if constexpr (KIND != 0) {
+        staged_tile<STAGE, T, KIND>(p, io, tile, bufs);
+      } else {
+        const int tx = (int)(tile % p.tiles[0]);
+        const int ty = (int)((tile / p.tiles[0]) % p.tiles[1]);
+        const int tzi = (int)(tile / ((long long)p.tiles[0] * p.tiles[1]));
+        const int lx = (int)threadIdx.x % p.ltx, ly = (int)threadIdx.x / p.ltx;
+        const int i = tx * p.ltx + lx, j = ty * p.lty + ly;
+        if (ly < p.lty && i < G.n[0] && j < G.n[1]) {
+          const int k0 = tzi * p.tz, k1 = min(k0 + p.tz, G.n[2]);
+          for (int k = k0; k < k1; ++k) {
+            const long long q = i + (long long)j * G.sy + (long long)k * G.sz;
+            T rhs[V_N];
+            GSrc src{io.yin + G.off0 + q, G.sv, G.sy, G.sz};
+            bssn_rhs_point<T>(src, p.W, p.P, rhs);
+            bssn_store<STAGE, T>(io, G, q, i, j, k, rhs, false);
+          }
         }
       }
     } else {
@@ -256,7 +311,18 @@ const Tile kCandidates[] = {{64, 4, 1}, {64, 4, 2}, {64, 4, 4}, {32, 8, 1}, {32,
 int size_class(const int32_t n[3]) { return n[0] <= 40 ? 0 : (n[0] <= 72 ? 1 : 2); }
 
 std::mutex g_table_mu;
-std::map<std::pair<int, int>, Tile> g_table;  // (precision, class) -> tuned tile
+std::map<std::pair<int, int>, Tile> g_table;  // (precision, class) -> tuned tile (kind 0)
+std::map<int, int> g_kind;                    // precision -> tuned kernel kind
+
+// CHEMORA_BATCH_KIND=0|1|2 forces the kernel kind of new plans (ablation
+// switch, read at every plan build)
+int default_kind(int precision) {
+  const char* e = std::getenv("CHEMORA_BATCH_KIND");
+  if (e && (e[0] == '0' || e[0] == '1' || e[0] == '2') && e[1] == 0) return e[0] - '0';
+  std::lock_guard<std::mutex> lk(g_table_mu);
+  auto it = g_kind.find(precision);
+  return it != g_kind.end() ? it->second : 1;  // untuned: staged 32x8
+}
 
 // model score (lower is better): padded-thread waste from ragged tiles, times
 // the halo re-read factor of the tile's cache footprint
@@ -297,6 +363,7 @@ struct Plan {
   std::vector<Tile> tiles;
   double dt = 0.0;
   int precision = 0;
+  int kind = 0;
   int np = 0;
   long long n_interior = 0, n_total = 0;
   int grid_blocks = 0;
@@ -315,14 +382,35 @@ void destroy_plan(Plan* p) {
   delete p;
 }
 
-int persistent_blocks() {
+int compute_units() {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
       cus = prop.multiProcessorCount;
   }
-  return cus * 2;  // two resident workgroups per CU (one wave per SIMD each)
+  return cus;
+}
+
+// Persistent grid: as many workgroups as can be resident at once (registers
+// and LDS of the kernel instance decide), so that none waits for a slot.
+template <typename T, int KIND>
+int resident_blocks() {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_stage_kernel<1, T, KIND>,
+                                                   kThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return compute_units() * per_cu;
+}
+
+int persistent_blocks(int precision, int kind) {
+  const bool mixed = precision == CHEMORA_MIXED;
+  switch (kind) {
+    case 1: return mixed ? resident_blocks<float, 1>() : resident_blocks<double, 1>();
+    case 2: return mixed ? resident_blocks<float, 2>() : resident_blocks<double, 2>();
+    default: return mixed ? resident_blocks<float, 0>() : resident_blocks<double, 0>();
+  }
 }
 
 int validate_patches(const chemora_patch* patches, int32_t np, int* precision) {
@@ -348,10 +436,11 @@ int validate_patches(const chemora_patch* patches, int32_t np, int* precision) {
 
 // Build descriptors and the work list, upload to meta (synchronously).
 int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, double dt,
-               int precision, const Tile* forced) {
+               int precision, int kind, const Tile* forced) {
   P->np = np;
   P->dt = dt;
   P->precision = precision;
+  P->kind = kind;
   P->grids.resize(np);
   P->states.resize(np);
   P->wss.resize(np);
@@ -365,7 +454,9 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     P->wss[q] = patches[q].workspace;
     const Geo& G = grid_geo(g);
     const int32_t n[3] = {G.n[0], G.n[1], G.n[2]};
-    const Tile t = forced ? *forced : default_tile(n, precision);
+    const Tile t = kind == 1   ? Tile{32, 8, 1}
+                   : kind == 2 ? Tile{16, 16, 1}
+                               : (forced ? *forced : default_tile(n, precision));
     P->tiles[q] = t;
     PatchDesc& d = pd[q];
     d.G = G;
@@ -412,7 +503,7 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     e = hipMemcpy(m + MetaLayout::gprefix_off(np), gprefix.data(), 8 * (np + 1),
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) return device_status(e, "batch plan upload");
-  P->grid_blocks = persistent_blocks();
+  P->grid_blocks = persistent_blocks(precision, kind);
   const double tout[5] = {0.0, 0.5, 0.5, 1.0, 1.0};
   for (int s = 0; s <= 4; ++s) {
     Batch& b = P->batch[s];
@@ -430,23 +521,32 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
   return CHEMORA_OK;
 }
 
-template <typename T>
+template <typename T, int KIND>
 hipError_t launch_stage(const Plan* P, int s, hipStream_t st) {
   const dim3 grid(P->grid_blocks), block(kThreads);
   const Batch& b = P->batch[s];
   switch (s) {
-    case 0: hipLaunchKernelGGL((batch_stage_kernel<0, T>), grid, block, 0, st, b); break;
-    case 1: hipLaunchKernelGGL((batch_stage_kernel<1, T>), grid, block, 0, st, b); break;
-    case 2: hipLaunchKernelGGL((batch_stage_kernel<2, T>), grid, block, 0, st, b); break;
-    case 3: hipLaunchKernelGGL((batch_stage_kernel<3, T>), grid, block, 0, st, b); break;
-    default: hipLaunchKernelGGL((batch_stage_kernel<4, T>), grid, block, 0, st, b); break;
+    case 0: hipLaunchKernelGGL((batch_stage_kernel<0, T, KIND>), grid, block, 0, st, b); break;
+    case 1: hipLaunchKernelGGL((batch_stage_kernel<1, T, KIND>), grid, block, 0, st, b); break;
+    case 2: hipLaunchKernelGGL((batch_stage_kernel<2, T, KIND>), grid, block, 0, st, b); break;
+    case 3: hipLaunchKernelGGL((batch_stage_kernel<3, T, KIND>), grid, block, 0, st, b); break;
+    default: hipLaunchKernelGGL((batch_stage_kernel<4, T, KIND>), grid, block, 0, st, b); break;
   }
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_kind(const Plan* P, int s, hipStream_t st) {
+  switch (P->kind) {
+    case 1: return launch_stage<T, 1>(P, s, st);
+    case 2: return launch_stage<T, 2>(P, s, st);
+    default: return launch_stage<T, 0>(P, s, st);
+  }
+}
+
 hipError_t launch_any(const Plan* P, int s, hipStream_t st) {
-  return P->precision == CHEMORA_MIXED ? launch_stage<float>(P, s, st)
-                                       : launch_stage<double>(P, s, st);
+  return P->precision == CHEMORA_MIXED ? launch_kind<float>(P, s, st)
+                                       : launch_kind<double>(P, s, st);
 }
 
 // capture: S1, S2, S3, S4, clock += dt
@@ -469,6 +569,18 @@ int capture_graph(Plan* P) {
   if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
   hipStreamDestroy(cs);
   return device_status(e, "batch graph capture");
+}
+
+// Time three right-hand-side launches (stage 0 writes the first stage buffer;
+// states are untouched) of a plan after one warm-up launch.
+int time_plan(const Plan* P, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  hipError_t e = launch_any(P, 0, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+  for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_any(P, 0, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  return device_status(e, "autotune trial");
 }
 
 bool same_patches(const Plan* P, const chemora_patch* patches, int32_t np, double dt) {
@@ -525,7 +637,7 @@ int chemora_batch_step(const chemora_patch* patches, int32_t npatches, void* met
         delete P;
         return device_status(e, "batch plan");
       }
-      st = build_plan(P, patches, npatches, meta, dt, precision, nullptr);
+      st = build_plan(P, patches, npatches, meta, dt, precision, default_kind(precision), nullptr);
       if (st == CHEMORA_OK) st = capture_graph(P);
       if (st != CHEMORA_OK) {
         destroy_plan(P);
@@ -565,7 +677,8 @@ int chemora_batch_release(void* meta) {
 int chemora_batch_tile(const int32_t n[3], int32_t precision, int32_t tile[3]) {
   if (!n || !tile) return fail(CHEMORA_ERR_INVALID, "NULL argument");
   if (n[0] < 1 || n[1] < 1 || n[2] < 1) return fail(CHEMORA_ERR_INVALID, "n must be >= 1");
-  const Tile t = default_tile(n, precision);
+  const int kind = default_kind(precision);
+  const Tile t = kind == 1 ? Tile{32, 8, 1} : kind == 2 ? Tile{16, 16, 1} : default_tile(n, precision);
   tile[0] = t.ltx;
   tile[1] = t.lty;
   tile[2] = t.tz;
@@ -622,21 +735,10 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
     float best_ms = 1e30f;
     for (size_t c = 0; c < scored.size() && c < 4; ++c) {
       Plan P;
-      st = build_plan(&P, ps.data(), (int)ps.size(), meta, 0.0, precision, &scored[c].second);
-      if (st != CHEMORA_OK) break;
-      // trial: right-hand side only (stage 0 writes the first stage buffer;
-      // states are untouched), one warm-up and three timed launches
-      hipError_t e = launch_any(&P, 0, nullptr);
-      if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
-      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_any(&P, 0, nullptr);
-      if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      st = build_plan(&P, ps.data(), (int)ps.size(), meta, 0.0, precision, 0, &scored[c].second);
       float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        st = device_status(e, "autotune trial");
-        break;
-      }
+      if (st == CHEMORA_OK) st = time_plan(&P, e0, e1, &ms);
+      if (st != CHEMORA_OK) break;
       if (ms < best_ms) {
         best_ms = ms;
         best = scored[c].second;
@@ -655,6 +757,26 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
              ps.size());
     json += buf;
     first = false;
+  }
+  // kernel kind: per-patch global-load tiles (as just tuned) against the
+  // two staged kinds, each timed over the whole batch
+  float kind_ms[3] = {0.f, 0.f, 0.f};
+  int best_kind = 0;
+  for (int kind = 0; kind < 3 && st == CHEMORA_OK; ++kind) {
+    Plan P;
+    st = build_plan(&P, patches, npatches, meta, 0.0, precision, kind, nullptr);
+    if (st == CHEMORA_OK) st = time_plan(&P, e0, e1, &kind_ms[kind]);
+    if (st == CHEMORA_OK && kind_ms[kind] < kind_ms[best_kind]) best_kind = kind;
+  }
+  if (st == CHEMORA_OK) {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    g_kind[precision] = best_kind;
+    char buf[256];
+    snprintf(buf, sizeof buf,
+             "%s  \"precision%d_kind\": {\"kind\": %d, \"ms_per_rhs\": [%.5f, %.5f, %.5f]}",
+             first ? "" : ",\n", precision, best_kind, kind_ms[0] / 3.0, kind_ms[1] / 3.0,
+             kind_ms[2] / 3.0);
+    json += buf;
   }
   json += "\n}\n";
   hipEventDestroy(e0);

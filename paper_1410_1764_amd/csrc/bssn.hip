@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(TX * TY) bssn_lds_kernel(BssnArgs a) {
   // register footprint
   const int k = bz;
   LSrc<TX, TY> src;
-  src.init(G, a.io.yin, lds, x0, y0, k, tx, ty);
+  src.init(G, a.io.yin, lds, lds + S::TOTAL, x0, y0, k, tx, ty);
   src.prefetch(kRhsOrder[0]);
   T rhs[V_N];
   bssn_rhs_point<T>(src, a.W, a.P, rhs);

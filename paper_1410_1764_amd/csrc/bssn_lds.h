@@ -65,7 +65,8 @@ struct LAcc {
 template <int TX, int TY>
 struct LSrc {
   using S = LdsShape<TX, TY>;
-  double* lds;       // 2 * TOTAL doubles
+  double* lds0;      // buffer for even-numbered grid functions (TOTAL doubles)
+  double* lds1;      // buffer for odd-numbered ones
   const double* Yt;  // yin + off0: tile addressing base (variable 0)
   const double* Yc;  // centre value of variable 0 at the thread's (clamped) point
   long long sv;
@@ -75,9 +76,10 @@ struct LSrc {
   int seq;               // grid functions acquired at this point so far
 
   // tile origin (x0, y0), plane k, thread position (tx, ty)
-  __device__ __forceinline__ void init(const Geo& G, const double* yin, double* shared, int x0,
-                                       int y0, int k, int tx, int ty) {
-    lds = shared;
+  __device__ __forceinline__ void init(const Geo& G, const double* yin, double* buf0,
+                                       double* buf1, int x0, int y0, int k, int tx, int ty) {
+    lds0 = buf0;
+    lds1 = buf1;
     Yt = yin + G.off0;
     sv = G.sv;
     const int tid = ty * TX + tx;
@@ -125,7 +127,7 @@ struct LSrc {
 
   // the staged neighbourhood of grid function kRhsOrder[seq] (== v)
   __device__ __forceinline__ LAcc<TX, TY> acquire(int /*v*/) {
-    double* buf = lds + (seq & 1) * S::TOTAL;
+    double* buf = (seq & 1) ? lds1 : lds0;
     const int tid = (int)threadIdx.x;
 #pragma unroll
     for (int m = 0; m < S::SLOTS; ++m) {

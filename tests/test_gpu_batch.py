@@ -67,6 +67,27 @@ def test_batch_matches_oracle_per_patch(precision, tol):
     C.batch_release(meta)
 
 
+@pytest.mark.parametrize("kind", ["0", "1", "2"])
+@pytest.mark.parametrize("precision,tol", [(C.FP64, 1e-12), (C.MIXED, 1e-5)])
+def test_batch_kernel_kinds_match_oracle(kind, precision, tol, monkeypatch):
+    """Each kernel kind (per-patch cached-load tiles; LDS-staged 32x8 and
+    16x16 tiles) on uneven patches whose sizes leave ragged tiles."""
+    monkeypatch.setenv("CHEMORA_BATCH_KIND", kind)
+    specs = SMALL[:2] + [{"n": (19, 13, 11), "h": 1 / 64, "origin": (0.7, 0.1, 0.4)}]
+    grids, blocks, states, wss, y0s = _patches(specs, precision, seed=11)
+    meta = torch.empty(C.batch_meta_bytes(len(grids)) // 8, dtype=torch.float64, device="cuda")
+    dt = 0.25 / 128
+    C.batch_step(grids, states, wss, meta, 0.0, dt, 2)
+    torch.cuda.synchronize()
+    C.batch_release(meta)
+    for q, (g, b, st, y0) in enumerate(zip(grids, blocks, states, y0s)):
+        yo = b.embed(y0)
+        oracle.rk4(b, oracle.BSSN, oracle.BC_GAUGEWAVE, yo, 0.0, dt, 2)
+        e = parity(g.download(st), b.interior(yo))
+        print("kind", kind, "patch", q, e.max(), I.BSSN_NAMES[int(np.argmax(e))])
+        assert e.max() <= tol
+
+
 def test_batch_equals_single_grid_path_and_replays():
     grids, blocks, states, wss, y0s = _patches(SMALL, C.FP64)
     meta = torch.empty(C.batch_meta_bytes(len(grids)) // 8, dtype=torch.float64, device="cuda")
@@ -84,7 +105,7 @@ def test_batch_equals_single_grid_path_and_replays():
     C.batch_release(meta)
 
 
-def test_autotune_keeps_results_bitwise():
+def test_autotune_keeps_results():
     specs = [{"n": tuple(int(v) for v in p["n"]), "h": p["h"], "origin": p["origin"]}
              for p in I.patch_list(I.SEED0 + 4, 6, 24, 56)]
     grids, blocks, states, wss, y0s = _patches(specs, C.FP64)
@@ -99,6 +120,9 @@ def test_autotune_keeps_results_bitwise():
     C.autotune(grids, states, wss, meta, None)
     C.batch_step(grids, states, wss, meta, 0.0, dt, 2)
     torch.cuda.synchronize()
+    # the tuned plan may use another kernel kind: same arithmetic per point,
+    # equal up to rounding
     for g, s, b in zip(grids, states, before):
-        assert np.array_equal(g.download(s), b)
+        a = g.download(s)
+        assert np.abs(a - b).max() <= 1e-15 * np.abs(b).max()
     C.batch_release(meta)
