@@ -9,8 +9,9 @@ inputs resident in HBM.  value = 128^3 * steps / elapsed.
 
 Also measured (reported in the same JSON line): the mixed-precision path,
 the fused RK4 step at 128^3 (FP64 and mixed), the scalar wave RK4 step at
-256^3, the constraint kernel, and a streaming copy (achievable HBM
-bandwidth).  Single GPU only.
+256^3, the constraint kernel, the batched path over 64 uneven patches
+(autotuned, graph-captured; FP64 and mixed), and a streaming copy
+(achievable HBM bandwidth).  Single GPU only.
 """
 from __future__ import annotations
 
@@ -29,17 +30,29 @@ HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
 FP64_PEAK = 78.6e12        # FLOP/s, MI355X vector FP64
 FP32_PEAK = 157.3e12       # FLOP/s, MI355X vector FP32 (packed); unpacked issues at half
 BSSN_BYTES_PER_PT = 24 * 8 * 2       # read every variable once, write every rhs once
-# FP64 operations per point of the right-hand-side kernel are counted
-# statically from its gfx950 ISA by paper_1410_1764_amd/isa_count.py (the
-# kernel is branch-free per point) into profiles/bssn_rhs_flops.json.
+# Floating-point operations per point of the default right-hand-side kernels
+# are counted statically from their gfx950 ISA (the point code is
+# branch-free) by paper_1410_1764_amd/isa_count.py into
+# paper_1410_1764_amd/kernel_facts.json; the same file holds the HBM traffic
+# per launch measured with hardware counters, valid only while the hash of
+# the kernel sources matches.
+KERNEL_FP64 = "bssn_async_kernel<0,double,32,8,6>"
+KERNEL_MIXED = "bssn_lds_kernel<0,float,32,8>"
+# Mixed precision runs unpacked FP32 (packed FP32 is disabled at compile
+# time), which issues at the FP64 vector rate: 256 CUs x 4 SIMDs x 16 lanes
+# x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s.
+UNPACKED_PEAK = 78.6e12
 
 
-def _flops_per_point():
-    p = os.path.join(ROOT, "profiles", "bssn_rhs_flops.json")
-    if os.path.exists(p):
-        with open(p) as f:
-            return json.load(f)
-    return None
+def _facts():
+    from paper_1410_1764_amd import isa_count
+    if not os.path.exists(isa_count.FACTS):
+        return None
+    with open(isa_count.FACTS) as f:
+        facts = json.load(f)
+    tr = facts.get("traffic")
+    facts["traffic_valid"] = bool(tr) and tr.get("source_hash") == isa_count.source_hash()
+    return facts
 
 
 def _events_time(fn, reps):
@@ -61,6 +74,7 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-patch batch timing")
     ap.add_argument("--only-rhs", action="store_true",
                     help="time only the FP64 right-hand side (for profiler runs)")
     args = ap.parse_args(argv)
@@ -121,7 +135,9 @@ def main(argv=None) -> int:
         a = torch.empty(nb // 8, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         kc = _events_time(lambda: C.probe_copy(b, a, nb), 2)
-        print(json.dumps({"rhs_fp64_ms": k64 * 1e3, "copy_512MiB_ms": kc * 1e3}))
+        kmx = _events_time(lambda: gmx.rhs(st, rhs), reps)
+        print(json.dumps({"rhs_fp64_ms": k64 * 1e3, "rhs_mixed_ms": kmx * 1e3,
+                          "copy_512MiB_ms": kc * 1e3}))
         return 0
 
     for _ in range(args.warmup):
@@ -166,6 +182,43 @@ def main(argv=None) -> int:
     kwmx = _events_time(lambda: gwmx.rk4_step(sw, wsw, 0.0, 0.25 * hw, 10), 2) / 10
     del sw, wsw
 
+    # batch: 64 uneven patches (24..96 per axis, three refinement levels),
+    # analytic gauge-wave ghosts, one graph-captured persistent launch per
+    # substage, autotuned; 20 RK4 steps timed per precision
+    batch = {}
+    if not args.no_batch:
+        import tempfile
+        specs = I.patch_list(I.SEED0 + 4, 64, 24, 96)
+        npts = sum(int(np.prod(p["n"])) for p in specs)
+        dtb = 0.25 * min(p["h"] for p in specs)
+        for name, prec in (("fp64", C.FP64), ("mixed", C.MIXED)):
+            grids, states, wss = [], [], []
+            for p in specs:
+                g = C.Grid(p["n"], 3, p["h"], origin=p["origin"], system=C.BSSN, precision=prec,
+                           boundary=C.BC_GAUGEWAVE, slicing=C.SLICING_HARMONIC,
+                           shift=C.SHIFT_FROZEN, gw_amp=0.1, gw_wavelength=1.0, gw_axis=0)
+                grids.append(g)
+                states.append(g.upload(I.gaugewave(p["n"], p["h"], p["origin"], 0.1, 1.0, 0)))
+                wss.append(g.new_workspace())
+            meta = torch.empty(C.batch_meta_bytes(len(grids)) // 8, dtype=torch.float64,
+                               device="cuda")
+            with tempfile.TemporaryDirectory() as td:
+                tpath = os.path.join(td, "tune.json")
+                C.autotune(grids, states, wss, meta, tpath)
+                with open(tpath) as f:
+                    table = json.load(f)
+            C.batch_step(grids, states, wss, meta, 0.0, dtb, 1)
+            kb = _events_time(lambda: C.batch_step(grids, states, wss, meta, dtb, dtb, 20), 1) / 20
+            C.batch_release(meta)
+            kind = next((v["kind"] for k, v in table.items() if k.endswith("_kind")), None)
+            batch[name] = {"ms_per_step": kb * 1e3, "point_steps_per_s": npts / kb,
+                           "rhs_updates_per_s": 4 * npts / kb, "kernel_kind": kind}
+            del grids, states, wss, meta
+            torch.cuda.synchronize()
+        batch["points"] = npts
+        batch["patches"] = len(specs)
+        print("[bench] batch done", file=sys.stderr, flush=True)
+
     # streaming copy: achievable bandwidth and the counter calibration kernel
     nbytes = 1 << 30
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -180,30 +233,39 @@ def main(argv=None) -> int:
     # ---- roofline of the dominant kernel (right-hand side, FP64): both the
     # HBM bound (algorithmic bytes) and the FP64 ALU bound (counted flops);
     # "roofline" is the one whose ideal time is longer, i.e. the binding one
-    fl = _flops_per_point()
+    fl = _facts()
     bytes_launch = BSSN_BYTES_PER_PT * pts
+    traffic64 = traffic_mx = None
+    if fl and fl["traffic_valid"]:
+        traffic64 = fl["traffic"].get("fp64_bytes_per_launch")
+        traffic_mx = fl["traffic"].get("mixed_bytes_per_launch")
     roof_hbm = {"bound": "hbm", "achieved": bytes_launch / k64 / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": bytes_launch / k64 / HBM_PEAK, "traffic": None,
-                "kernel": "bssn_stage_kernel<0,double>", "kernel_ms": k64 * 1e3,
+                "unit": "GB/s", "frac": bytes_launch / k64 / HBM_PEAK, "traffic": traffic64,
+                "kernel": KERNEL_FP64, "kernel_ms": k64 * 1e3,
                 "bytes_per_point": BSSN_BYTES_PER_PT, "points_per_launch": pts}
-    tr = (fl or {}).get("traffic_fp64_bytes_per_launch")
-    if tr:
-        roof_hbm["traffic"] = tr
     roof = roof_hbm
     roof_other = None
+    roof_mx = {"bound": "hbm", "achieved": bytes_launch / kmx / 1e9, "peak": HBM_PEAK / 1e9,
+               "unit": "GB/s", "frac": bytes_launch / kmx / HBM_PEAK, "traffic": traffic_mx,
+               "kernel": KERNEL_MIXED, "kernel_ms": kmx * 1e3}
     if fl:
         f64 = fl["fp64"]["flops_per_point"]
         roof_alu = {"bound": "alu", "achieved": f64 * pts / k64 / 1e12, "peak": FP64_PEAK / 1e12,
                     "unit": "TFLOP/s", "frac": f64 * pts / k64 / FP64_PEAK,
-                    "traffic": roof_hbm["traffic"], "kernel": roof_hbm["kernel"],
+                    "traffic": traffic64, "kernel": KERNEL_FP64,
                     "kernel_ms": k64 * 1e3, "flops_per_point": f64, "points_per_launch": pts}
         if f64 * pts / FP64_PEAK > bytes_launch / HBM_PEAK:
             roof, roof_other = roof_alu, roof_hbm
         else:
             roof_other = roof_alu
-    roof_mx = {"bound": "hbm", "achieved": bytes_launch / kmx / 1e9, "peak": HBM_PEAK / 1e9,
-               "unit": "GB/s", "frac": bytes_launch / kmx / HBM_PEAK,
-               "kernel": "bssn_stage_kernel<0,float>", "kernel_ms": kmx * 1e3}
+        fmx = fl["mixed"]["f32_flops_per_point"] + fl["mixed"]["f64_flops_per_point"]
+        if fmx * pts / UNPACKED_PEAK > bytes_launch / HBM_PEAK:
+            roof_mx = {"bound": "alu", "achieved": fmx * pts / kmx / 1e12,
+                       "peak": UNPACKED_PEAK / 1e12, "unit": "TFLOP/s",
+                       "frac": fmx * pts / kmx / UNPACKED_PEAK, "traffic": traffic_mx,
+                       "kernel": KERNEL_MIXED, "kernel_ms": kmx * 1e3,
+                       "flops_per_point": fmx, "points_per_launch": pts,
+                       "note": "f32 (unpacked) and f64 vector operations, both at 78.6 TFLOP/s"}
 
     # ---- CPU baseline: the oracle on the host cores (rank 0, N = 1 only)
     cpu = None
@@ -252,6 +314,7 @@ def main(argv=None) -> int:
                     "wave256_rk4_GBps_fp64": 272 * nw ** 3 / kw64 / 1e9,
                     "wave256_rk4_GBps_mixed": 272 * nw ** 3 / kwmx / 1e9,
                     "copy_GBps": copy_bw / 1e9},
+        "batch64": batch or None,
     }
     print(json.dumps(out), flush=True)
     return 0

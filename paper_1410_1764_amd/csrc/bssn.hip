@@ -12,6 +12,7 @@
 //   bssn_stage_kernel (ablation, CHEMORA_BSSN_KERNEL=global): stencil
 //     neighbours are read straight from global memory through L1/L2.
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 
@@ -27,8 +28,19 @@ struct BssnArgs {
   StageIO io;
   int ltx, lty, zc;
   int tiles[3];
+  int cols[2];  // column split of the staged kernels (column_tile); 0: xcd_tile order
   int images;
 };
+
+// tile of workgroup b in the single-plane (staged) kernels
+__device__ __forceinline__ bool plane_tile(const BssnArgs& a, int b, int& bx, int& by, int& bz) {
+  if (a.cols[0] > 0) return column_tile(b, a.tiles, a.cols[0], a.cols[1], bx, by, bz);
+  const int t = xcd_tile(b, a.tiles[0] * a.tiles[1] * a.tiles[2]);
+  bx = t % a.tiles[0];
+  by = (t / a.tiles[0]) % a.tiles[1];
+  bz = t / (a.tiles[0] * a.tiles[1]);
+  return true;
+}
 
 // CHEMORA_BSSN_WAVES: minimum waves per SIMD the register allocator must
 // allow (an ablation switch; 1 lets the FP64 kernel use VGPRs + AGPRs).
@@ -62,10 +74,8 @@ __global__ void __launch_bounds__(TX * TY) bssn_lds_kernel(BssnArgs a) {
   using S = LdsShape<TX, TY>;
   __shared__ double lds[2 * S::TOTAL];
   const Geo& G = a.G;
-  const int nb = a.tiles[0] * a.tiles[1] * a.tiles[2];
-  const int b = xcd_tile(blockIdx.x, nb);
-  const int bx = b % a.tiles[0], by = (b / a.tiles[0]) % a.tiles[1];
-  const int bz = b / (a.tiles[0] * a.tiles[1]);
+  int bx, by, bz;
+  if (!plane_tile(a, blockIdx.x, bx, by, bz)) return;  // whole workgroup: no barrier yet
   const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
   const int x0 = bx * TX, y0 = by * TY;
   const int i = x0 + tx, j = y0 + ty;
@@ -93,10 +103,8 @@ __global__ void __launch_bounds__(TX * TY) bssn_async_kernel(BssnArgs a) {
       L5[S::TOTAL];
   double* const bufs[6] = {L0, L1, L2, L3, L4, L5};
   const Geo& G = a.G;
-  const int nb = a.tiles[0] * a.tiles[1] * a.tiles[2];
-  const int b = xcd_tile(blockIdx.x, nb);
-  const int bx = b % a.tiles[0], by = (b / a.tiles[0]) % a.tiles[1];
-  const int k = b / (a.tiles[0] * a.tiles[1]);
+  int bx, by, k;
+  if (!plane_tile(a, blockIdx.x, bx, by, k)) return;  // whole workgroup: no barrier yet
   const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
   const int x0 = bx * TX, y0 = by * TY;
   const int i = x0 + tx, j = y0 + ty;
@@ -110,14 +118,28 @@ __global__ void __launch_bounds__(TX * TY) bssn_async_kernel(BssnArgs a) {
                          a.images != 0);
 }
 
-// CHEMORA_BSSN_TILE=64|32|16 forces the tile width (ablation switch)
-int forced_tile_width() {
-  static const int w = [] {
+// CHEMORA_BSSN_TILE=WxH forces the tile of the staged kernels (64x4, 32x8,
+// 16x16: 256 threads; 16x8: 128; 16x4, 8x8: 64), and a single width W the
+// tile W x (256 / W) (ablation switch)
+struct TileShape {
+  int w, h;
+};
+TileShape forced_tile() {
+  static const TileShape t = [] {
     const char* e = std::getenv("CHEMORA_BSSN_TILE");
-    const int v = e ? std::atoi(e) : 0;
-    return (v == 64 || v == 32 || v == 16) ? v : 0;
+    TileShape r{0, 0};
+    if (!e) return r;
+    int w = 0, h = 0;
+    if (std::sscanf(e, "%dx%d", &w, &h) == 2) {
+      r = {w, h};
+    } else if (std::sscanf(e, "%d", &w) == 1) {
+      r = {w, w > 0 ? 256 / w : 0};
+    }
+    const bool ok = (r.w == 64 && r.h == 4) || (r.w == 32 && r.h == 8) ||
+                    (r.w == 16 && (r.h == 16 || r.h == 8 || r.h == 4)) || (r.w == 8 && r.h == 8);
+    return ok ? r : TileShape{0, 0};
   }();
-  return w;
+  return t;
 }
 
 // Kernel choice (measured at 128^3): FP64 -> async staging (five grid
@@ -140,18 +162,36 @@ int kernel_variant(int precision) {
   return o >= 0 ? o : (precision == CHEMORA_MIXED ? 1 : 2);
 }
 
+// CHEMORA_BSSN_ORDER=plane restores the XCD-contiguous plane order of the
+// staged kernels instead of the column walk (ablation switch)
+bool column_order() {
+  static const bool v = [] {
+    const char* e = std::getenv("CHEMORA_BSSN_ORDER");
+    return !(e && std::strcmp(e, "plane") == 0);
+  }();
+  return v;
+}
+
 template <int STAGE, typename T>
 void launch_shape(const BssnArgs& a, dim3 grid, hipStream_t s) {
-  const int variant = kernel_variant(sizeof(T) == 4 ? CHEMORA_MIXED : CHEMORA_FP64);
+  int variant = kernel_variant(sizeof(T) == 4 ? CHEMORA_MIXED : CHEMORA_FP64);
+  const int nt = a.ltx * a.lty;
+  if (variant == 1 && nt != 256) variant = 2;  // the prefetched LDS source needs 256 threads
   if (variant == 0) {
     hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T>), grid, dim3(256), 0, s, a);
   } else if (variant == 2) {
     if (a.ltx == 64)
-      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 64, 4, 5>), grid, dim3(256), 0, s, a);
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 64, 4, 5>), grid, dim3(nt), 0, s, a);
     else if (a.ltx == 32)
-      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 32, 8, 6>), grid, dim3(256), 0, s, a);
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 32, 8, 6>), grid, dim3(nt), 0, s, a);
+    else if (a.ltx == 8)
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 8, 8, 5>), grid, dim3(nt), 0, s, a);
+    else if (a.lty == 4)
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 4, 5>), grid, dim3(nt), 0, s, a);
+    else if (a.lty == 8)
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 8, 6>), grid, dim3(nt), 0, s, a);
     else
-      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 16, 6>), grid, dim3(256), 0, s, a);
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 16, 6>), grid, dim3(nt), 0, s, a);
   } else if (a.ltx == 64) {
     hipLaunchKernelGGL((bssn_lds_kernel<STAGE, T, 64, 4>), grid, dim3(256), 0, s, a);
   } else if (a.ltx == 32) {
@@ -184,8 +224,14 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
   a.io = io;
   a.images = images ? 1 : 0;
   a.ltx = G.n[0] >= 24 ? 32 : 16;
-  if (forced_tile_width()) a.ltx = forced_tile_width();
   a.lty = 256 / a.ltx;
+  if (kernel_variant(precision) != 0 && forced_tile().w) {
+    a.ltx = forced_tile().w;
+    a.lty = forced_tile().h;
+  } else if (forced_tile().w && forced_tile().w * forced_tile().h == 256) {
+    a.ltx = forced_tile().w;
+    a.lty = forced_tile().h;
+  }
   a.tiles[0] = (G.n[0] + a.ltx - 1) / a.ltx;
   a.tiles[1] = (G.n[1] + a.lty - 1) / a.lty;
   const long long xy = (long long)a.tiles[0] * a.tiles[1];
@@ -197,7 +243,17 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
   if (zsplit < 1) zsplit = 1;
   a.zc = (G.n[2] + zsplit - 1) / zsplit;
   a.tiles[2] = (G.n[2] + a.zc - 1) / a.zc;
-  const dim3 grid((unsigned)(a.tiles[0] * a.tiles[1] * a.tiles[2]));
+  long long blocks = (long long)a.tiles[0] * a.tiles[1] * a.tiles[2];
+  a.cols[0] = a.cols[1] = 0;
+  if (kernel_variant(precision) != 0 && column_order()) {
+    const ColumnSplit c = column_split(a.tiles, a.ltx, a.lty);
+    if (c.cx > 0) {
+      a.cols[0] = c.cx;
+      a.cols[1] = c.cy;
+      blocks = c.blocks_per_plane * a.tiles[2];
+    }
+  }
+  const dim3 grid((unsigned)blocks);
   return precision == CHEMORA_MIXED ? launch_t<float>(stage, a, grid, s)
                                     : launch_t<double>(stage, a, grid, s);
 }

@@ -541,20 +541,43 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
 // output may alias nothing here, but the compiler cannot know that, and a
 // load after a store to a possibly aliasing address would serialise the
 // 24 updates into 24 memory round trips.
+// Streaming hints for the pointwise traffic of a substage (outputs, y_n and
+// the accumulator are touched once per launch): nontemporal accesses keep
+// them from evicting the stencil planes that neighbouring tiles still need
+// from L2.  CHEMORA_STREAM_HINTS=0 turns them off (ablation switch).
+#ifndef CHEMORA_STREAM_HINTS
+#define CHEMORA_STREAM_HINTS 1
+#endif
+__device__ __forceinline__ void st_stream(double* p, double v) {
+#if CHEMORA_STREAM_HINTS
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+__device__ __forceinline__ double ld_stream(const double* p) {
+#if CHEMORA_STREAM_HINTS
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
 template <int STAGE, typename T>
 __device__ __forceinline__ void bssn_store(const StageIO& io, const Geo& G, long long p, int i,
                                            int j, int k, const T rhs[V_N], bool images) {
   double* out = io.out + G.off0;
   if (STAGE == 0) {
 #pragma unroll
-    for (int v = 0; v < V_N; ++v) out[p + v * G.sv] = (double)rhs[v];
+    for (int v = 0; v < V_N; ++v) st_stream(out + p + v * G.sv, (double)rhs[v]);
     return;
   }
   double y0[V_N], ac[V_N];
 #pragma unroll
   for (int v = 0; v < V_N; ++v) {
-    y0[v] = io.y0[G.off0 + p + v * G.sv];
-    ac[v] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? io.acc[G.off0 + p + v * G.sv] : 0.0;
+    y0[v] = ld_stream(io.y0 + G.off0 + p + v * G.sv);
+    ac[v] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? ld_stream(io.acc + G.off0 + p + v * G.sv)
+                                                      : 0.0;
   }
 #pragma unroll
   for (int v = 0; v < V_N; ++v) {
@@ -562,15 +585,19 @@ __device__ __forceinline__ void bssn_store(const StageIO& io, const Geo& G, long
     const double kv = (double)rhs[v];
     double nv;
     if (STAGE == 1) {
-      io.acc[G.off0 + q] = kv;
+      st_stream(io.acc + G.off0 + q, kv);
       nv = y0[v] + io.cdt * kv;
     } else if (STAGE == 2 || STAGE == 3) {
-      io.acc[G.off0 + q] = ac[v] + 2.0 * kv;
+      st_stream(io.acc + G.off0 + q, ac[v] + 2.0 * kv);
       nv = y0[v] + io.cdt * kv;
     } else {
       nv = y0[v] + io.cdt * (ac[v] + kv);
     }
-    store_with_images(out + v * G.sv, G, i, j, k, nv, images);
+    if (images) {
+      store_with_images(out + v * G.sv, G, i, j, k, nv, true);
+    } else {
+      st_stream(out + q, nv);
+    }
   }
 }
 

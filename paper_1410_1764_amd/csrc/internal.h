@@ -55,6 +55,52 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return x * q + (x < r ? x : r) + l;
 }
 
+// XCD column walk for single-plane tiles.  The xy tile grid is cut into
+// cx x cy columns (cx * cy == kNumXcd, cx <= tiles[0], cy <= tiles[1]); the
+// workgroups that land on XCD x (b % 8 == x) take column x's tiles plane by
+// plane, so that the planes just below and above those in flight are still
+// in that XCD's L2 when the next planes need them (z stencils reach 3
+// planes each way).  A grid of 8 x (largest column) x tiles[2] blocks;
+// blocks past the end of a smaller column get no tile (returns false).
+__host__ __device__ __forceinline__ bool column_tile(int b, const int tiles[3], int cx, int cy, int& bx,
+                                            int& by, int& bz) {
+  const int x = b % kNumXcd, l = b / kNumXcd;
+  const int ux = x % cx, uy = x / cx;
+  const int xlo = ux * tiles[0] / cx, xhi = (ux + 1) * tiles[0] / cx;
+  const int ylo = uy * tiles[1] / cy, yhi = (uy + 1) * tiles[1] / cy;
+  const int wx = xhi - xlo, ncol = wx * (yhi - ylo);
+  bz = l / ncol;
+  if (bz >= tiles[2]) return false;
+  const int r = l - bz * ncol;
+  bx = xlo + r % wx;
+  by = ylo + r / wx;
+  return true;
+}
+
+// Host: the column split for a tiles[0] x tiles[1] plane of ltx x lty tiles
+// (the smallest largest column, then the smallest column perimeter), or
+// {0, 0} when the plane has too few tiles for eight columns.
+struct ColumnSplit {
+  int cx, cy;
+  long long blocks_per_plane;  // 8 x the largest column
+};
+inline ColumnSplit column_split(const int tiles[2], int ltx, int lty) {
+  ColumnSplit best{0, 0, 0};
+  long long best_max = 0, best_per = 0;
+  for (int cx = 1; cx <= kNumXcd; cx *= 2) {
+    const int cy = kNumXcd / cx;
+    if (cx > tiles[0] || cy > tiles[1]) continue;
+    const long long mx = (tiles[0] + cx - 1) / cx, my = (tiles[1] + cy - 1) / cy;
+    const long long m = mx * my, per = mx * ltx + my * lty;
+    if (best.cx == 0 || m < best_max || (m == best_max && per < best_per)) {
+      best = {cx, cy, kNumXcd * m};
+      best_max = m;
+      best_per = per;
+    }
+  }
+  return best;
+}
+
 // Periodic write-through: store v at interior point (i,j,k) of one grid
 // function and at every periodic image of it that lies in the ghost zones.
 __device__ __forceinline__ void store_with_images(double* f, const Geo& G, int i, int j, int k,

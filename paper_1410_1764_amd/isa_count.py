@@ -7,7 +7,11 @@ per grid point (plus a handful of index operations outside the point loop).
 FLOPs: v_fma/v_fmac = 2; add, sub, mul, ldexp (a multiply by a power of two),
 rcp and sqrt = 1; conversions and selects are not counted.
 
-Writes profiles/bssn_rhs_flops.json (read by bench.py for the ALU roofline).
+Counts the default kernels (FP64: async-staged 32x8 tiles; mixed: LDS-staged
+32x8 tiles) and writes paper_1410_1764_amd/kernel_facts.json, which bench.py
+reads for the ALU roofline.  The same file carries the HBM traffic per launch
+measured with hardware counters, keyed by a hash of the kernel sources so that
+a stale figure is not reported once the kernel has changed.
 Usage: python -m paper_1410_1764_amd.isa_count
 """
 from __future__ import annotations
@@ -27,6 +31,20 @@ OPS = {
             "v_subrev_f32": 1, "v_rcp_f32": 1, "v_sqrt_f32": 1, "v_fmamk_f32": 2,
             "v_fmaak_f32": 2, "v_mac_f32": 2, "v_div_fmas_f32": 2, "v_ldexp_f32": 1},
 }
+
+
+FACTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "kernel_facts.json")
+KERNEL_SOURCES = ("bssn.hip", "bssn_lds.h", "bssn_point.h", "internal.h")
+
+
+def source_hash() -> str:
+    """SHA-256 over the sources of the right-hand-side kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def kernel_bodies(asm: str):
@@ -62,25 +80,25 @@ def main():
     result = {"source": "paper_1410_1764_amd/csrc/bssn.hip", "arch": B.ARCH,
               "command": "python -m paper_1410_1764_amd.isa_count"}
     for name, body in kernel_bodies(asm):
-        if "bssn_stage_kernelILi0EdE" in name:
+        if "bssn_async_kernelILi0EdLi32ELi8ELi6E" in name:
             c = count(body)
             result["fp64"] = {"kernel": name, "flops_per_point": c["f64"]["flops_per_point"],
                               "instructions": c["f64"]["instructions"],
                               "global_loads": c["global_load"], "scratch_ops": c["scratch"]}
-        if "bssn_stage_kernelILi0EfE" in name:
+        if "bssn_lds_kernelILi0EfLi32ELi8E" in name:
             c = count(body)
             result["mixed"] = {"kernel": name, "f32_flops_per_point": c["f32"]["flops_per_point"],
                                "f64_flops_per_point": c["f64"]["flops_per_point"],
                                "instructions": {**c["f32"]["instructions"],
                                                 **c["f64"]["instructions"]},
                                "global_loads": c["global_load"], "scratch_ops": c["scratch"]}
-    path = os.path.join(B.ROOT, "profiles", "bssn_rhs_flops.json")
+    result["source_hash"] = source_hash()
+    path = FACTS
     old = {}
     if os.path.exists(path):
         old = json.load(open(path))
-    for k in ("traffic_fp64_bytes_per_launch", "traffic_note"):
-        if k in old:
-            result[k] = old[k]
+    if "traffic" in old:
+        result["traffic"] = old["traffic"]
     with open(path, "w") as f:
         json.dump(result, f, indent=1)
     print(json.dumps(result, indent=1))
