@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -197,6 +198,14 @@ int chemora_fill_ghosts(chemora_grid* grid, double* state, double t, chemora_str
   }
 }
 
+static bool periodic_images() {
+  static const bool v = [] {
+    const char* e = std::getenv("CHEMORA_PERIODIC");
+    return e && std::strcmp(e, "images") == 0;
+  }();
+  return v;
+}
+
 static hipError_t launch_stage(const chemora_grid* g, int stage, bool images, const StageIO& io,
                                hipStream_t s) {
   if (g->d.system == CHEMORA_WAVE)
@@ -242,6 +251,12 @@ int chemora_rk4_step(chemora_grid* grid, double* state, void* workspace, double 
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool periodic = grid->d.boundary == CHEMORA_BC_PERIODIC;
+  // periodic ghosts: a separate fill of the stage output (default), or the
+  // stage kernels writing every value to its images as well
+  // (CHEMORA_PERIODIC=images, ablation switch).  The fill is the faster one:
+  // image stores make most boundary tiles' waves branch and issue scattered
+  // stores for all 24 grid functions.
+  const bool images = periodic && periodic_images();
   int st = chemora_fill_ghosts(grid, state, t, stream);
   if (st != CHEMORA_OK) return st;
   const double cdt[5] = {0.0, 0.5 * dt, 0.5 * dt, dt, dt / 6.0};
@@ -252,9 +267,13 @@ int chemora_rk4_step(chemora_grid* grid, double* state, void* workspace, double 
     double* outs[5] = {nullptr, B1, B2, B1, state};
     for (int stage = 1; stage <= 4; ++stage) {
       StageIO io{ins[stage], state, acc, outs[stage], cdt[stage]};
-      st = device_status(launch_stage(grid, stage, periodic, io, s), "RK4 substage launch");
+      st = device_status(launch_stage(grid, stage, images, io, s), "RK4 substage launch");
       if (st != CHEMORA_OK) return st;
-      if (!periodic) {
+      if (periodic && !images) {
+        st = device_status(launch_fill_periodic(grid->geo, grid->nvars, outs[stage], s),
+                           "periodic ghost fill");
+        if (st != CHEMORA_OK) return st;
+      } else if (!periodic) {
         st = device_status(launch_fill_gaugewave(grid->geo, grid->par, tn + ct[stage] * dt,
                                                  outs[stage], s),
                            "gauge-wave ghost fill");
