@@ -59,13 +59,13 @@ struct PatchDesc {
   Geo G;
   BssnPar P;
   Weights W;
-  double* state;
-  double* ws;         // B1 | B2 | acc, each E doubles
+  long long state_off;  // byte offset of the patch's state from Batch::base
+  long long ws_off;     // same for its workspace: B1 | B2 | acc, each E doubles
   long long E;        // elements of one state
   long long ghosts;   // ghost points of one grid function
   int ltx, lty, tz;   // tile: ltx * lty threads, tz planes each
   int tiles[3];
-  int pad;
+  int cols[2];        // column split of the xy tile grid (work-list order), 1 x 1: none
 };
 
 // Device plan buffer: patch descriptors, prefix sums of interior and ghost
@@ -79,6 +79,12 @@ struct MetaLayout {
 };
 
 struct Batch {
+  // Every patch pointer is base + a byte offset: derived from a kernel
+  // argument, the compiler knows it is global memory and uses global loads
+  // and stores (a pointer read from the descriptor would be generic, and
+  // its accesses FLAT instructions, which also count in the LDS wait counter
+  // and stall the LDS-staged kernels).
+  char* base;
   const PatchDesc* pd;
   const long long* prefix;   // interior items before patch q (work-list order)
   const long long* gprefix;  // ghost items before patch q
@@ -89,6 +95,33 @@ struct Batch {
   double t_out;   // stage-output time offset in units of dt (0.5, 0.5, 1, 1)
   int stage_io;   // 1..4, or 0 (right-hand side only, into B1)
 };
+
+// Tile of a patch's l-th interior item.  A patch's items are listed column
+// by column (cols[0] x cols[1] columns of the xy tile grid), each column
+// plane by plane: cut into eight contiguous shares, one per XCD, the list
+// makes every XCD walk columns along z (as column_tile does for one block),
+// so the planes above and below the ones in flight stay in its L2.
+__host__ __device__ __forceinline__ void patch_tile(const PatchDesc& p, long long l, int& bx, int& by,
+                                           int& bz) {
+  const int cx = p.cols[0], cy = p.cols[1];
+  long long base = 0;
+  for (int c = 0; c < cx * cy; ++c) {
+    const int ux = c % cx, uy = c / cx;
+    const int xlo = ux * p.tiles[0] / cx, xhi = (ux + 1) * p.tiles[0] / cx;
+    const int ylo = uy * p.tiles[1] / cy, yhi = (uy + 1) * p.tiles[1] / cy;
+    const int wx = xhi - xlo;
+    const long long per = (long long)wx * (yhi - ylo), n = per * p.tiles[2];
+    if (l < base + n || c == cx * cy - 1) {
+      const long long r = l - base;
+      bz = (int)(r / per);
+      const int t = (int)(r - bz * per);
+      bx = xlo + t % wx;
+      by = ylo + t / wx;
+      return;
+    }
+    base += n;
+  }
+}
 
 __device__ __forceinline__ int find_patch(const long long* prefix, int np, long long item) {
   int lo = 0, hi = np - 1;  // last q with prefix[q] <= item
@@ -165,19 +198,25 @@ __device__ __forceinline__ void gw_store(const BssnPar& P, double xa, double t, 
   for (int q = 0; q < V_N; ++q) f[q * sv] = v[q];
 }
 
-__device__ __forceinline__ void stage_buffers(const PatchDesc& p, int io, StageIO& s,
-                                              double dt) {
-  double* B1 = p.ws;
-  double* B2 = p.ws + p.E;
-  double* acc = p.ws + 2 * p.E;
-  s.y0 = p.state;
+__device__ __forceinline__ double* patch_state(const Batch& B, const PatchDesc& p) {
+  return reinterpret_cast<double*>(B.base + p.state_off);
+}
+
+__device__ __forceinline__ void stage_buffers(const Batch& B, const PatchDesc& p, int io,
+                                              StageIO& s, double dt) {
+  double* const state = patch_state(B, p);
+  double* const ws = reinterpret_cast<double*>(B.base + p.ws_off);
+  double* B1 = ws;
+  double* B2 = ws + p.E;
+  double* acc = ws + 2 * p.E;
+  s.y0 = state;
   s.acc = acc;
   switch (io) {
-    case 0: s.yin = p.state; s.out = B1; s.cdt = 0.0; break;
-    case 1: s.yin = p.state; s.out = B1; s.cdt = 0.5 * dt; break;
+    case 0: s.yin = state; s.out = B1; s.cdt = 0.0; break;
+    case 1: s.yin = state; s.out = B1; s.cdt = 0.5 * dt; break;
     case 2: s.yin = B1; s.out = B2; s.cdt = 0.5 * dt; break;
     case 3: s.yin = B2; s.out = B1; s.cdt = dt; break;
-    default: s.yin = B1; s.out = p.state; s.cdt = dt / 6.0; break;
+    default: s.yin = B1; s.out = state; s.cdt = dt / 6.0; break;
   }
 }
 
@@ -193,9 +232,8 @@ __device__ __forceinline__ void staged_tile(const PatchDesc& p, const StageIO& i
                                             double* const* bufs) {
   constexpr int TX = KindShape<KIND>::TX, TY = KindShape<KIND>::TY;
   const Geo& G = p.G;
-  const int bx = (int)(tile % p.tiles[0]);
-  const int by = (int)((tile / p.tiles[0]) % p.tiles[1]);
-  const int k = (int)(tile / ((long long)p.tiles[0] * p.tiles[1]));
+  int bx, by, k;
+  patch_tile(p, tile, bx, by, k);
   const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
   const int x0 = bx * TX, y0 = by * TY;
   const int i = x0 + tx, j = y0 + ty;
@@ -225,26 +263,65 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
   __shared__ double L0[TOT], L1[TOT], L2[TOT], L3[TOT], L4[TOT], L5[TOT];
   double* bufs[6] = {L0, L1, NB > 2 ? L2 : nullptr, NB > 2 ? L3 : nullptr,
                      NB > 2 ? L4 : nullptr, NB > 2 ? L5 : nullptr};
+  __shared__ long long s_lo, s_hi;  // item range of s_patch (interior or ghost)
+  // The current patch's descriptor lives in LDS: under register pressure the
+  // compiler re-reads descriptor fields (weights, strides) inside the point
+  // code; from global memory every such read would be followed by a vmcnt
+  // wait that also drains the stencil copies in flight, from LDS it waits
+  // on lgkmcnt only.
+  __shared__ PatchDesc s_pd;
+  __shared__ int s_changed;
   const double tnow = *B.clock;
-  for (long long item = blockIdx.x; item < B.n_total; item += gridDim.x) {
-    const bool interior = item < B.n_interior;
+  // XCD x (blockIdx.x % 8) takes share x of the interior items and share x
+  // of the ghost items, in list order; its gridDim.x / 8 blocks stride it
+  const int x = (int)blockIdx.x % kNumXcd;
+  const long long R = gridDim.x / kNumXcd;
+  const long long ni = B.n_interior, ng = B.n_total - B.n_interior;
+  const long long i0 = ni * x / kNumXcd, i1 = ni * (x + 1) / kNumXcd;
+  const long long g0 = ng * x / kNumXcd, g1 = ng * (x + 1) / kNumXcd;
+  const long long share = (i1 - i0) + (g1 - g0);
+  if (threadIdx.x == 0) {
+    s_lo = 0;
+    s_hi = -1;
+  }
+  for (long long t = blockIdx.x / kNumXcd; t < share; t += R) {
+    const bool interior = t < i1 - i0;
+    const long long item = interior ? i0 + t : ni + g0 + (t - (i1 - i0));
     __syncthreads();  // the previous item is finished by every wave
-    if (threadIdx.x == 0)
-      s_patch = interior ? find_patch(B.prefix, B.np, item)
-                         : find_patch(B.gprefix, B.np, item - B.n_interior);
+    if (threadIdx.x == 0) {
+      s_changed = 0;
+      if (!(item >= s_lo && item < s_hi)) {
+        // consecutive items of a block mostly stay in one patch: search only
+        // when the item leaves the current patch's range
+        const int q = interior ? find_patch(B.prefix, B.np, item)
+                               : find_patch(B.gprefix, B.np, item - ni);
+        s_patch = q;
+        s_lo = interior ? B.prefix[q] : ni + B.gprefix[q];
+        s_hi = interior ? B.prefix[q + 1] : ni + B.gprefix[q + 1];
+        s_changed = 1;
+      }
+    }
     __syncthreads();
-    const PatchDesc& p = B.pd[s_patch];
+    if (s_changed) {  // the same value in every thread
+      static_assert(sizeof(PatchDesc) % 8 == 0, "descriptor copied in 8-byte words");
+      const unsigned long long* from =
+          reinterpret_cast<const unsigned long long*>(B.pd + s_patch);
+      unsigned long long* to = reinterpret_cast<unsigned long long*>(&s_pd);
+      for (int w = (int)threadIdx.x; w < (int)(sizeof(PatchDesc) / 8); w += kThreads)
+        to[w] = from[w];
+      __syncthreads();
+    }
+    const PatchDesc& p = s_pd;
     const Geo& G = p.G;
     StageIO io;
-    stage_buffers(p, B.stage_io, io, B.dt);
+    stage_buffers(B, p, B.stage_io, io, B.dt);
     if (interior) {
       const long long tile = item - B.prefix[s_patch];
       if constexpr (KIND != 0) {
         staged_tile<STAGE, T, KIND>(p, io, tile, bufs);
       } else {
-        const int tx = (int)(tile % p.tiles[0]);
-        const int ty = (int)((tile / p.tiles[0]) % p.tiles[1]);
-        const int tzi = (int)(tile / ((long long)p.tiles[0] * p.tiles[1]));
+        int tx, ty, tzi;
+        patch_tile(p, tile, tx, ty, tzi);
         const int lx = (int)threadIdx.x % p.ltx, ly = (int)threadIdx.x / p.ltx;
         const int i = tx * p.ltx + lx, j = ty * p.lty + ly;
         if (ly < p.lty && i < G.n[0] && j < G.n[1]) {
@@ -291,7 +368,7 @@ __global__ void __launch_bounds__(kThreads) batch_state_ghosts_kernel(Batch B) {
       ghost_ijk(p.G, gq, ijk);
       const int a = p.P.gw_axis;
       const double xa = p.P.origin[a] + ijk[a] * p.P.h[a];
-      gw_store(p.P, xa, t, p.state + p.G.off0 + ijk[0] + (long long)ijk[1] * p.G.sy +
+      gw_store(p.P, xa, t, patch_state(B, p) + p.G.off0 + ijk[0] + (long long)ijk[1] * p.G.sy +
                                (long long)ijk[2] * p.G.sz, p.G.sv);
     }
   }
@@ -462,8 +539,8 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     d.G = G;
     d.P = grid_par(g);
     d.W = make_weights(d.P.h);
-    d.state = patches[q].state;
-    d.ws = static_cast<double*>(patches[q].workspace);
+    d.state_off = reinterpret_cast<char*>(patches[q].state) - reinterpret_cast<char*>(patches[0].state);
+    d.ws_off = static_cast<char*>(patches[q].workspace) - reinterpret_cast<char*>(patches[0].state);
     d.E = grid_state_elems(g);
     const long long e0 = G.n[0] + 2 * G.g, e1 = G.n[1] + 2 * G.g;
     d.ghosts = 2LL * G.g * e1 * e0 + (long long)G.n[2] * 2 * G.g * e0 +
@@ -474,7 +551,15 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     d.tiles[0] = (G.n[0] + t.ltx - 1) / t.ltx;
     d.tiles[1] = (G.n[1] + t.lty - 1) / t.lty;
     d.tiles[2] = (G.n[2] + t.tz - 1) / t.tz;
-    d.pad = 0;
+    // staged kinds: eight columns when the plane has enough tiles
+    d.cols[0] = d.cols[1] = 1;
+    if (kind != 0) {
+      const ColumnSplit c = column_split(d.tiles, t.ltx, t.lty);
+      if (c.cx > 0) {
+        d.cols[0] = c.cx;
+        d.cols[1] = c.cy;
+      }
+    }
     cost[q] = (long long)G.n[0] * G.n[1] * G.n[2];
   }
   // work-list order: patches by decreasing cost (LPT), so the biggest tiles
@@ -503,10 +588,12 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     e = hipMemcpy(m + MetaLayout::gprefix_off(np), gprefix.data(), 8 * (np + 1),
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) return device_status(e, "batch plan upload");
-  P->grid_blocks = persistent_blocks(precision, kind);
+  // a multiple of 8 (one share of the work list per XCD)
+  P->grid_blocks = std::max(kNumXcd, persistent_blocks(precision, kind) / kNumXcd * kNumXcd);
   const double tout[5] = {0.0, 0.5, 0.5, 1.0, 1.0};
   for (int s = 0; s <= 4; ++s) {
     Batch& b = P->batch[s];
+    b.base = reinterpret_cast<char*>(patches[0].state);
     b.pd = reinterpret_cast<const PatchDesc*>(m + MetaLayout::desc_off());
     b.prefix = reinterpret_cast<const long long*>(m + MetaLayout::prefix_off(np));
     b.gprefix = reinterpret_cast<const long long*>(m + MetaLayout::gprefix_off(np));
