@@ -16,9 +16,9 @@
 //
 // Three kernel kinds share this structure: kind 0 reads stencil neighbours
 // through the caches with a tile shape per patch (size class); kinds 1 and 2
-// stage each grid function's tile neighbourhood in LDS (bssn_lds.h: async
-// copies in FP64, register-prefetched LDS in mixed precision) with 32x8 or
-// 16x16 single-plane tiles.  The autotuner picks the kind and, for kind 0,
+// stage each grid function's tile neighbourhood in LDS with async copies
+// (bssn_lds.h, ASrc, in both precisions) with 32x8 or 16x16 single-plane
+// tiles.  The autotuner picks the kind and, for kind 0,
 // the tile of each size class.
 //
 // The four substage launches and a one-thread clock update (t += dt) are
@@ -238,16 +238,9 @@ __device__ __forceinline__ void staged_tile(const PatchDesc& p, const StageIO& i
   const int x0 = bx * TX, y0 = by * TY;
   const int i = x0 + tx, j = y0 + ty;
   T rhs[V_N];
-  if constexpr (std::is_same<T, double>::value) {
-    ASrc<TX, TY, 6> src;
-    src.init(G, io.yin, bufs, x0, y0, k, tx, ty);
-    bssn_rhs_point<T>(src, p.W, p.P, rhs);
-  } else {
-    LSrc<TX, TY> src;
-    src.init(G, io.yin, bufs[0], bufs[1], x0, y0, k, tx, ty);
-    src.prefetch(kRhsOrder[0]);
-    bssn_rhs_point<T>(src, p.W, p.P, rhs);
-  }
+  ASrc<TX, TY, 6> src;
+  src.init(G, io.yin, bufs, x0, y0, k, tx, ty);
+  bssn_rhs_point<T>(src, p.W, p.P, rhs);
   if (i < G.n[0] && j < G.n[1])
     bssn_store<STAGE, T>(io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
                          false);
@@ -257,12 +250,10 @@ template <int STAGE, typename T, int KIND>
 __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
   __shared__ int s_patch;
   constexpr int TOT = KindShape<KIND>::TOT;
-  constexpr int NB = KIND == 0 ? 0 : (std::is_same<T, double>::value ? 6 : 2);
-  // separate arrays, one per staging buffer (see bssn_lds.h); only the ones
-  // referenced by this kind and precision are allocated
+  // separate arrays, one per staging buffer (see bssn_lds.h); a tiny
+  // placeholder each for kind 0
   __shared__ double L0[TOT], L1[TOT], L2[TOT], L3[TOT], L4[TOT], L5[TOT];
-  double* bufs[6] = {L0, L1, NB > 2 ? L2 : nullptr, NB > 2 ? L3 : nullptr,
-                     NB > 2 ? L4 : nullptr, NB > 2 ? L5 : nullptr};
+  double* bufs[6] = {L0, L1, L2, L3, L4, L5};
   __shared__ long long s_lo, s_hi;  // item range of s_patch (interior or ghost)
   // The current patch's descriptor lives in LDS: under register pressure the
   // compiler re-reads descriptor fields (weights, strides) inside the point
