@@ -63,7 +63,8 @@ class _Params(ctypes.Structure):
                 ("slicing", ctypes.c_int), ("shift", ctypes.c_int),
                 ("shift_F", ctypes.c_double), ("eta", ctypes.c_double),
                 ("gw_amp", ctypes.c_double), ("gw_d", ctypes.c_double),
-                ("gw_axis", ctypes.c_int)]
+                ("gw_axis", ctypes.c_int), ("ko_sigma", ctypes.c_double),
+                ("enforce", ctypes.c_int)]
 
 
 _lib = None
@@ -91,6 +92,7 @@ def _load():
     lib.orc_rk4.restype = ctypes.c_int
     lib.orc_bssn_constraints.argtypes = [P, _DP, _DP, _DP]
     lib.orc_stencil.argtypes = [P, _DP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _DP, _DP]
+    lib.orc_bssn_enforce.argtypes = [P, _DP]
     _lib = lib
     return lib
 
@@ -114,7 +116,8 @@ class Block:
     """
 
     def __init__(self, n, g, h, origin=(0.0, 0.0, 0.0), slicing=0, shift=1,
-                 shift_F=0.75, eta=2.0, gw_amp=0.1, gw_d=1.0, gw_axis=0):
+                 shift_F=0.75, eta=2.0, gw_amp=0.1, gw_d=1.0, gw_axis=0, ko_sigma=0.0,
+                 enforce=0):
         self.n = tuple(int(v) for v in n)
         self.g = int(g)
         self.h = tuple(float(v) for v in (h if np.ndim(h) else (h, h, h)))
@@ -129,6 +132,8 @@ class Block:
         p.origin[:] = self.origin
         p.slicing, p.shift, p.shift_F, p.eta = self.slicing, self.shift, self.shift_F, self.eta
         p.gw_amp, p.gw_d, p.gw_axis = self.gw_amp, self.gw_d, self.gw_axis
+        self.ko_sigma, self.enforce = float(ko_sigma), int(enforce)
+        p.ko_sigma, p.enforce = self.ko_sigma, self.enforce
         self._p = p
 
     @property
@@ -213,7 +218,15 @@ def constraints(b: Block, y: np.ndarray, want_fields: bool = True):
 
 def stencil(b: Block, f: np.ndarray, kind: int, a: int, bdir: int = 0,
             sgn: np.ndarray | None = None) -> np.ndarray:
-    """kind 1: centred d_a; 2: centred d_a d_b; 3: lopsided d_a (side by sign of sgn)"""
+    """kind 1: centred d_a; 2: centred d_a d_b; 3: lopsided d_a (side by sign of sgn);
+    4: sixth difference along a (Kreiss-Oliger stencil, unscaled)"""
     out = np.zeros_like(f)
     _load().orc_stencil(ctypes.byref(b._p), _ptr(f), kind, a, bdir, _ptr(sgn), _ptr(out))
     return out
+
+
+def enforce(b: Block, y: np.ndarray) -> None:
+    """In place at interior points: det gt = 1 (gt scaled by det^-1/3), then
+    tr At = 0 with respect to the rescaled metric."""
+    assert y.shape[0] == NVAR[BSSN]
+    _load().orc_bssn_enforce(ctypes.byref(b._p), _ptr(y))

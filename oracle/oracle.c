@@ -110,6 +110,21 @@ static double fd11(const double* f, long sa, long sb, double ha, double hb) {
 /* lopsided first derivative, shifted one point towards the upwind side
  * chosen by the sign of the advecting velocity: weights (-3, -10, 18, -6, 1)
  * at offsets (-1, 0, 1, 2, 3) for vel >= 0, mirrored for vel < 0 */
+/* sixth difference along stride s, on neighbour differences:
+ * f3 - 6 f2 + 15 f1 - 20 f0 + 15 f-1 - 6 f-2 + f-3
+ * = [(f3-f0)+(f-3-f0)] - 6 [(f2-f0)+(f-2-f0)] + 15 [(f1-f0)+(f-1-f0)].
+ * Kreiss-Oliger dissipation for a 4th-order scheme adds
+ * (sigma / 64) sum_d delta6_d u / h_d to du/dt: the (-1)^(p+1) sigma
+ * h^(2p-1) / 2^(2p) (D+ D-)^p form with p = 3; its symbol is
+ * -(sigma / h) sin^6(theta / 2), so it damps every mode and vanishes on
+ * polynomials of degree <= 5. */
+static double delta6(const double* f, long s) {
+  const double s1 = (f[s] - f[0]) + (f[-s] - f[0]);
+  const double s2 = (f[2 * s] - f[0]) + (f[-2 * s] - f[0]);
+  const double s3 = (f[3 * s] - f[0]) + (f[-3 * s] - f[0]);
+  return (s3 - 6.0 * s2) + 15.0 * s1;
+}
+
 static double fdup(const double* f, long s, double h, double vel) {
   const double f0 = f[0];
   if (vel >= 0.0)
@@ -305,6 +320,15 @@ static void bssn_point(const orc_params* p, const geom* G, const double* y, long
     const double* f = y + v * G->npts + q;
     adv[v] = 0.0;
     for (int k = 0; k < 3; k++) adv[v] += beta[k] * fdup(f, st[k], h[k], beta[k]);
+  }
+  /* Kreiss-Oliger dissipation of every variable (added to the right-hand
+   * sides in phase 3; the frozen shift and B stay frozen) */
+  double diss[NB];
+  for (int v = 0; v < NB; v++) {
+    const double* f = y + v * G->npts + q;
+    diss[v] = 0.0;
+    if (p->ko_sigma != 0.0)
+      for (int k = 0; k < 3; k++) diss[v] += (p->ko_sigma / 64.0) * delta6(f, st[k]) / h[k];
   }
 
   /* phase 2: derived quantities */
@@ -538,6 +562,12 @@ static void bssn_point(const orc_params* p, const geom* G, const double* y, long
       out[BB + i] = 0.0;
     }
   }
+
+  /* dissipation */
+  for (int v = 0; v < NB; v++) {
+    const int frozen = p->shift != 1 && v >= BETA;
+    if (!frozen) out[v] += diss[v];
+  }
 }
 
 void orc_bssn_rhs(const orc_params* p, const double* y, double* r) {
@@ -611,6 +641,55 @@ static void axpy_interior(const geom* G, int nvar, const double* y, double c,
   }
 }
 
+/* Algebraic constraints of the conformal variables at one point (stride
+ * between variables): rescale gt_ij by det(gt)^(-1/3) so that its
+ * determinant is 1, then remove the trace of At_ij with respect to the
+ * rescaled metric, At_ij -= gt_ij gt^kl At_kl / 3 (gt^kl = adjugate /
+ * determinant). */
+static void enforce_point(double* u, long stride) {
+  double gt[3][3], At[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      gt[i][j] = u[(GT + SYM[i][j]) * stride];
+      At[i][j] = u[(AT + SYM[i][j]) * stride];
+    }
+  const double det = gt[0][0] * (gt[1][1] * gt[2][2] - gt[1][2] * gt[2][1]) -
+                     gt[0][1] * (gt[1][0] * gt[2][2] - gt[1][2] * gt[2][0]) +
+                     gt[0][2] * (gt[1][0] * gt[2][1] - gt[1][1] * gt[2][0]);
+  const double sc = 1.0 / cbrt(det);
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) gt[i][j] *= sc;
+  const double det2 = gt[0][0] * (gt[1][1] * gt[2][2] - gt[1][2] * gt[2][1]) -
+                      gt[0][1] * (gt[1][0] * gt[2][2] - gt[1][2] * gt[2][0]) +
+                      gt[0][2] * (gt[1][0] * gt[2][1] - gt[1][1] * gt[2][0]);
+  double tr = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      const double gu = (gt[(j + 1) % 3][(i + 1) % 3] * gt[(j + 2) % 3][(i + 2) % 3] -
+                         gt[(j + 1) % 3][(i + 2) % 3] * gt[(j + 2) % 3][(i + 1) % 3]) /
+                        det2;
+      tr += gu * At[i][j];
+    }
+  for (int i = 0; i < 3; i++)
+    for (int j = i; j < 3; j++) {
+      u[(GT + SYM[i][j]) * stride] = gt[i][j];
+      u[(AT + SYM[i][j]) * stride] = At[i][j] - gt[i][j] * tr / 3.0;
+    }
+}
+
+/* enforce the algebraic constraints at every interior point */
+void orc_bssn_enforce(const orc_params* p, double* y) {
+  geom G = mkgeom(p);
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < G.n[2]; k++)
+    for (int j = 0; j < G.n[1]; j++)
+      for (int i = 0; i < G.n[0]; i++) enforce_point(y + idx(&G, i, j, k), G.npts);
+}
+
+static void maybe_enforce(const orc_params* p, int system, double* y) {
+  if (system == ORC_BSSN && p->enforce) orc_bssn_enforce(p, y);
+}
+
 int orc_rk4(const orc_params* p, int system, int bc, double* y, double t, double dt,
             int nsteps) {
   geom G = mkgeom(p);
@@ -630,12 +709,15 @@ int orc_rk4(const orc_params* p, int system, int bc, double* y, double t, double
     fill_ghosts(p, system, bc, t, y);
     rhs(p, system, y, k1);
     axpy_interior(&G, nvar, y, 0.5 * dt, k1, ys);
+    maybe_enforce(p, system, ys);
     fill_ghosts(p, system, bc, t + 0.5 * dt, ys);
     rhs(p, system, ys, k2);
     axpy_interior(&G, nvar, y, 0.5 * dt, k2, ys);
+    maybe_enforce(p, system, ys);
     fill_ghosts(p, system, bc, t + 0.5 * dt, ys);
     rhs(p, system, ys, k3);
     axpy_interior(&G, nvar, y, dt, k3, ys);
+    maybe_enforce(p, system, ys);
     fill_ghosts(p, system, bc, t + dt, ys);
     rhs(p, system, ys, k4);
     for (int v = 0; v < nvar; v++) {
@@ -648,6 +730,7 @@ int orc_rk4(const orc_params* p, int system, int bc, double* y, double t, double
             y[q] = y[q] + (dt / 6.0) * (((k1[q] + 2.0 * k2[q]) + 2.0 * k3[q]) + k4[q]);
           }
     }
+    maybe_enforce(p, system, y);
     t = t + dt;
   }
   fill_ghosts(p, system, bc, t, y);
@@ -659,7 +742,8 @@ int orc_rk4(const orc_params* p, int system, int bc, double* y, double t, double
 /* single stencil probe on interior points, for checking the operators on
  * their own: kind 1 = centred first derivative along a; kind 2 = centred
  * second derivative d_a d_b (pure when a == b, mixed otherwise); kind 3 =
- * lopsided derivative along a, upwind side from the sign of sgn (NULL: +). */
+ * lopsided derivative along a, upwind side from the sign of sgn (NULL: +);
+ * kind 4 = sixth difference along a (the Kreiss-Oliger stencil, unscaled). */
 void orc_stencil(const orc_params* p, const double* f, int kind, int a, int b,
                  const double* sgn, double* out) {
   geom G = mkgeom(p);
@@ -675,8 +759,10 @@ void orc_stencil(const orc_params* p, const double* f, int kind, int a, int b,
         else if (kind == 2)
           v = (a == b) ? fd2(f + q, st[a], p->h[a])
                        : fd11(f + q, st[a], st[b], p->h[a], p->h[b]);
-        else
+        else if (kind == 3)
           v = fdup(f + q, st[a], p->h[a], sgn ? sgn[q] : 1.0);
+        else
+          v = delta6(f + q, st[a]);
         out[q] = v;
       }
 }

@@ -36,6 +36,8 @@ typedef struct {
   double gw_amp;       /* gauge wave amplitude A */
   double gw_d;         /* gauge wave wavelength d */
   int gw_axis;         /* gauge wave direction 0,1,2 */
+  double ko_sigma;     /* Kreiss-Oliger dissipation strength (0: none) */
+  int enforce;         /* 1: det gt = 1 and tr At = 0 after every RK substage */
 } orc_params;
 
 enum { ORC_WAVE = 1, ORC_BSSN = 2, ORC_WAVE5 = 3 };
@@ -54,5 +56,6 @@ void orc_bssn_constraints(const orc_params* p, const double* y, double* hm,
                           double norms[4]);
 void orc_stencil(const orc_params* p, const double* f, int kind, int a, int b,
                  const double* sgn, double* out);
+void orc_bssn_enforce(const orc_params* p, double* y);
 
 #endif
