@@ -102,7 +102,11 @@ typedef struct {
   double gw_amp;     /* gauge wave amplitude A, |A| < 1 */
   double gw_wavelength; /* gauge wave wavelength d > 0 */
   int32_t gw_axis;   /* gauge wave direction 0, 1 or 2 */
-  int32_t reserved;  /* must be 0 */
+  int32_t enforce;   /* BSSN only (else 0): 1 = after every RK substage rescale gt_ij so
+                        that det gt = 1, then remove the trace of At_ij; 0 = off */
+  double ko_sigma;   /* BSSN only (else 0): Kreiss-Oliger dissipation strength >= 0,
+                        adding sigma/64 sum_d (sixth difference along d) / h_d to the
+                        right-hand side of every evolved variable; 0 = off */
 } chemora_grid_desc;
 
 /* Create a grid object from a description (copied).  Validates every field

@@ -99,7 +99,11 @@ int validate_desc(const chemora_grid_desc* d) {
     if (!std::isfinite(d->shift_F) || !std::isfinite(d->eta))
       return fail(CHEMORA_ERR_INVALID, "shift_F and eta must be finite");
   }
-  if (d->reserved != 0) return fail(CHEMORA_ERR_INVALID, "reserved field must be 0");
+  if (d->enforce != 0 && d->enforce != 1) return fail(CHEMORA_ERR_INVALID, "enforce must be 0 or 1");
+  if (!std::isfinite(d->ko_sigma) || d->ko_sigma < 0.0)
+    return fail(CHEMORA_ERR_INVALID, "ko_sigma must be finite and >= 0");
+  if (d->system != CHEMORA_BSSN && (d->enforce != 0 || d->ko_sigma != 0.0))
+    return fail(CHEMORA_ERR_INVALID, "enforce and ko_sigma apply to the BSSN system only");
   // element strides of a grid function must fit in 32 bits
   const long long e0 = d->n[0] + 2LL * d->ghost, e1 = d->n[1] + 2LL * d->ghost;
   const long long e2 = d->n[2] + 2LL * d->ghost;
@@ -148,6 +152,8 @@ int chemora_grid_create(const chemora_grid_desc* desc, chemora_grid** out) {
   P.gw_A = desc->gw_amp;
   P.gw_d = desc->gw_wavelength;
   P.gw_axis = desc->gw_axis;
+  P.enforce = desc->enforce;
+  P.ko_sigma = desc->ko_sigma;
   *out = g;
   return CHEMORA_OK;
 }

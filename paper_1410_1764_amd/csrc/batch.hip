@@ -227,7 +227,7 @@ struct KindShape {
 };
 
 // one single-plane tile of a staged kind
-template <int STAGE, typename T, int KIND>
+template <int STAGE, typename T, int KIND, int KOM>
 __device__ __forceinline__ void staged_tile(const PatchDesc& p, const StageIO& io, long long tile,
                                             double* const* bufs) {
   constexpr int TX = KindShape<KIND>::TX, TY = KindShape<KIND>::TY;
@@ -240,13 +240,15 @@ __device__ __forceinline__ void staged_tile(const PatchDesc& p, const StageIO& i
   T rhs[V_N];
   ASrc<TX, TY, 6> src;
   src.init(G, io.yin, bufs, x0, y0, k, tx, ty);
-  bssn_rhs_point<T>(src, p.W, p.P, rhs);
+  bssn_rhs_point<T, KOM>(src, p.W, p.P, rhs);
   if (i < G.n[0] && j < G.n[1])
     bssn_store<STAGE, T>(io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
-                         false);
+                         false, p.P.enforce != 0);
 }
 
-template <int STAGE, typename T, int KIND>
+// KOM: Kreiss-Oliger dissipation compiled in (KO_ON: patches with sigma = 0
+// add an exact zero) or out (KO_OFF: no patch dissipates)
+template <int STAGE, typename T, int KIND, int KOM>
 __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
   __shared__ int s_patch;
   constexpr int TOT = KindShape<KIND>::TOT;
@@ -309,7 +311,7 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
     if (interior) {
       const long long tile = item - B.prefix[s_patch];
       if constexpr (KIND != 0) {
-        staged_tile<STAGE, T, KIND>(p, io, tile, bufs);
+        staged_tile<STAGE, T, KIND, KOM>(p, io, tile, bufs);
       } else {
         int tx, ty, tzi;
         patch_tile(p, tile, tx, ty, tzi);
@@ -321,8 +323,8 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
             const long long q = i + (long long)j * G.sy + (long long)k * G.sz;
             T rhs[V_N];
             GSrc src{io.yin + G.off0 + q, G.sv, G.sy, G.sz};
-            bssn_rhs_point<T>(src, p.W, p.P, rhs);
-            bssn_store<STAGE, T>(io, G, q, i, j, k, rhs, false);
+            bssn_rhs_point<T, KOM>(src, p.W, p.P, rhs);
+            bssn_store<STAGE, T>(io, G, q, i, j, k, rhs, false, p.P.enforce != 0);
           }
         }
       }
@@ -432,6 +434,7 @@ struct Plan {
   double dt = 0.0;
   int precision = 0;
   int kind = 0;
+  bool ko = false;  // some patch has Kreiss-Oliger dissipation
   int np = 0;
   long long n_interior = 0, n_total = 0;
   int grid_blocks = 0;
@@ -462,23 +465,29 @@ int compute_units() {
 
 // Persistent grid: as many workgroups as can be resident at once (registers
 // and LDS of the kernel instance decide), so that none waits for a slot.
-template <typename T, int KIND>
+template <typename T, int KIND, int KOM>
 int resident_blocks() {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_stage_kernel<1, T, KIND>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_stage_kernel<1, T, KIND, KOM>,
                                                    kThreads, 0) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   return compute_units() * per_cu;
 }
 
-int persistent_blocks(int precision, int kind) {
-  const bool mixed = precision == CHEMORA_MIXED;
+template <typename T, int KOM>
+int persistent_blocks_t(int kind) {
   switch (kind) {
-    case 1: return mixed ? resident_blocks<float, 1>() : resident_blocks<double, 1>();
-    case 2: return mixed ? resident_blocks<float, 2>() : resident_blocks<double, 2>();
-    default: return mixed ? resident_blocks<float, 0>() : resident_blocks<double, 0>();
+    case 1: return resident_blocks<T, 1, KOM>();
+    case 2: return resident_blocks<T, 2, KOM>();
+    default: return resident_blocks<T, 0, KOM>();
   }
+}
+
+int persistent_blocks(int precision, int kind, bool ko) {
+  if (precision == CHEMORA_MIXED)
+    return ko ? persistent_blocks_t<float, KO_ON>(kind) : persistent_blocks_t<float, KO_OFF>(kind);
+  return ko ? persistent_blocks_t<double, KO_ON>(kind) : persistent_blocks_t<double, KO_OFF>(kind);
 }
 
 int validate_patches(const chemora_patch* patches, int32_t np, int* precision) {
@@ -509,6 +518,8 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
   P->dt = dt;
   P->precision = precision;
   P->kind = kind;
+  P->ko = false;
+  for (int q = 0; q < np; ++q) P->ko = P->ko || grid_par(patches[q].grid).ko_sigma != 0.0;
   P->grids.resize(np);
   P->states.resize(np);
   P->wss.resize(np);
@@ -529,7 +540,7 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     PatchDesc& d = pd[q];
     d.G = G;
     d.P = grid_par(g);
-    d.W = make_weights(d.P.h);
+    d.W = make_weights(d.P.h, d.P.ko_sigma);
     d.state_off = reinterpret_cast<char*>(patches[q].state) - reinterpret_cast<char*>(patches[0].state);
     d.ws_off = static_cast<char*>(patches[q].workspace) - reinterpret_cast<char*>(patches[0].state);
     d.E = grid_state_elems(g);
@@ -580,7 +591,7 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) return device_status(e, "batch plan upload");
   // a multiple of 8 (one share of the work list per XCD)
-  P->grid_blocks = std::max(kNumXcd, persistent_blocks(precision, kind) / kNumXcd * kNumXcd);
+  P->grid_blocks = std::max(kNumXcd, persistent_blocks(precision, kind, P->ko) / kNumXcd * kNumXcd);
   const double tout[5] = {0.0, 0.5, 0.5, 1.0, 1.0};
   for (int s = 0; s <= 4; ++s) {
     Batch& b = P->batch[s];
@@ -599,32 +610,33 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
   return CHEMORA_OK;
 }
 
-template <typename T, int KIND>
+template <typename T, int KIND, int KOM>
 hipError_t launch_stage(const Plan* P, int s, hipStream_t st) {
   const dim3 grid(P->grid_blocks), block(kThreads);
   const Batch& b = P->batch[s];
   switch (s) {
-    case 0: hipLaunchKernelGGL((batch_stage_kernel<0, T, KIND>), grid, block, 0, st, b); break;
-    case 1: hipLaunchKernelGGL((batch_stage_kernel<1, T, KIND>), grid, block, 0, st, b); break;
-    case 2: hipLaunchKernelGGL((batch_stage_kernel<2, T, KIND>), grid, block, 0, st, b); break;
-    case 3: hipLaunchKernelGGL((batch_stage_kernel<3, T, KIND>), grid, block, 0, st, b); break;
-    default: hipLaunchKernelGGL((batch_stage_kernel<4, T, KIND>), grid, block, 0, st, b); break;
+    case 0: hipLaunchKernelGGL((batch_stage_kernel<0, T, KIND, KOM>), grid, block, 0, st, b); break;
+    case 1: hipLaunchKernelGGL((batch_stage_kernel<1, T, KIND, KOM>), grid, block, 0, st, b); break;
+    case 2: hipLaunchKernelGGL((batch_stage_kernel<2, T, KIND, KOM>), grid, block, 0, st, b); break;
+    case 3: hipLaunchKernelGGL((batch_stage_kernel<3, T, KIND, KOM>), grid, block, 0, st, b); break;
+    default: hipLaunchKernelGGL((batch_stage_kernel<4, T, KIND, KOM>), grid, block, 0, st, b); break;
   }
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int KOM>
 hipError_t launch_kind(const Plan* P, int s, hipStream_t st) {
   switch (P->kind) {
-    case 1: return launch_stage<T, 1>(P, s, st);
-    case 2: return launch_stage<T, 2>(P, s, st);
-    default: return launch_stage<T, 0>(P, s, st);
+    case 1: return launch_stage<T, 1, KOM>(P, s, st);
+    case 2: return launch_stage<T, 2, KOM>(P, s, st);
+    default: return launch_stage<T, 0, KOM>(P, s, st);
   }
 }
 
 hipError_t launch_any(const Plan* P, int s, hipStream_t st) {
-  return P->precision == CHEMORA_MIXED ? launch_kind<float>(P, s, st)
-                                       : launch_kind<double>(P, s, st);
+  if (P->precision == CHEMORA_MIXED)
+    return P->ko ? launch_kind<float, KO_ON>(P, s, st) : launch_kind<float, KO_OFF>(P, s, st);
+  return P->ko ? launch_kind<double, KO_ON>(P, s, st) : launch_kind<double, KO_OFF>(P, s, st);
 }
 
 // capture: S1, S2, S3, S4, clock += dt

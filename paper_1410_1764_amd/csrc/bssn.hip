@@ -48,7 +48,7 @@ __device__ __forceinline__ bool plane_tile(const BssnArgs& a, int b, int& bx, in
 #define CHEMORA_BSSN_WAVES 1
 #endif
 
-template <int STAGE, typename T>
+template <int STAGE, typename T, int KOM>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(CHEMORA_BSSN_WAVES))) bssn_stage_kernel(BssnArgs a) {
   const Geo& G = a.G;
@@ -64,12 +64,12 @@ __attribute__((amdgpu_waves_per_eu(CHEMORA_BSSN_WAVES))) bssn_stage_kernel(BssnA
     const long long p = i + (long long)j * G.sy + (long long)k * G.sz;
     T rhs[V_N];
     GSrc src{a.io.yin + G.off0 + p, G.sv, G.sy, G.sz};
-    bssn_rhs_point<T>(src, a.W, a.P, rhs);
-    bssn_store<STAGE, T>(a.io, G, p, i, j, k, rhs, a.images != 0);
+    bssn_rhs_point<T, KOM>(src, a.W, a.P, rhs);
+    bssn_store<STAGE, T>(a.io, G, p, i, j, k, rhs, a.images != 0, a.P.enforce != 0);
   }
 }
 
-template <int STAGE, typename T, int TX, int TY>
+template <int STAGE, typename T, int TX, int TY, int KOM>
 __global__ void __launch_bounds__(TX * TY) bssn_lds_kernel(BssnArgs a) {
   using S = LdsShape<TX, TY>;
   __shared__ double lds[2 * S::TOTAL];
@@ -88,13 +88,13 @@ __global__ void __launch_bounds__(TX * TY) bssn_lds_kernel(BssnArgs a) {
   src.init(G, a.io.yin, lds, lds + S::TOTAL, x0, y0, k, tx, ty);
   src.prefetch(kRhsOrder[0]);
   T rhs[V_N];
-  bssn_rhs_point<T>(src, a.W, a.P, rhs);
+  bssn_rhs_point<T, KOM>(src, a.W, a.P, rhs);
   if (active)
     bssn_store<STAGE, T>(a.io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
-                         a.images != 0);
+                         a.images != 0, a.P.enforce != 0);
 }
 
-template <int STAGE, typename T, int TX, int TY, int NBUF>
+template <int STAGE, typename T, int TX, int TY, int NBUF, int KOM>
 __global__ void __launch_bounds__(TX * TY) bssn_async_kernel(BssnArgs a) {
   static_assert(NBUF >= 2 && NBUF <= 6, "1 to 5 grid functions in flight");
   using S = LdsShape<TX, TY>;
@@ -112,10 +112,10 @@ __global__ void __launch_bounds__(TX * TY) bssn_async_kernel(BssnArgs a) {
   ASrc<TX, TY, NBUF> src;
   src.init(G, a.io.yin, bufs, x0, y0, k, tx, ty);
   T rhs[V_N];
-  bssn_rhs_point<T>(src, a.W, a.P, rhs);
+  bssn_rhs_point<T, KOM>(src, a.W, a.P, rhs);
   if (active)
     bssn_store<STAGE, T>(a.io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
-                         a.images != 0);
+                         a.images != 0, a.P.enforce != 0);
 }
 
 // CHEMORA_BSSN_TILE=WxH forces the tile of the staged kernels (64x4, 32x8,
@@ -172,33 +172,45 @@ bool column_order() {
   return v;
 }
 
-template <int STAGE, typename T>
-void launch_shape(const BssnArgs& a, dim3 grid, hipStream_t s) {
+template <int STAGE, typename T, int KOM>
+void launch_shape_k(const BssnArgs& a, dim3 grid, hipStream_t s) {
   int variant = kernel_variant(sizeof(T) == 4 ? CHEMORA_MIXED : CHEMORA_FP64);
   const int nt = a.ltx * a.lty;
   if (variant == 1 && nt != 256) variant = 2;  // the prefetched LDS source needs 256 threads
   if (variant == 0) {
-    hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T, KOM>), grid, dim3(256), 0, s, a);
   } else if (variant == 2) {
-    if (a.ltx == 64)
-      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 64, 4, 5>), grid, dim3(nt), 0, s, a);
-    else if (a.ltx == 32)
-      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 32, 8, 6>), grid, dim3(nt), 0, s, a);
-    else if (a.ltx == 8)
-      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 8, 8, 5>), grid, dim3(nt), 0, s, a);
-    else if (a.lty == 4)
-      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 4, 5>), grid, dim3(nt), 0, s, a);
-    else if (a.lty == 8)
-      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 8, 6>), grid, dim3(nt), 0, s, a);
-    else
-      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 16, 6>), grid, dim3(nt), 0, s, a);
-  } else if (a.ltx == 64) {
-    hipLaunchKernelGGL((bssn_lds_kernel<STAGE, T, 64, 4>), grid, dim3(256), 0, s, a);
+    if (a.ltx == 32) {
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 32, 8, 6, KOM>), grid, dim3(nt), 0, s, a);
+    } else if (a.ltx == 16 && a.lty == 16) {
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 16, 6, KOM>), grid, dim3(nt), 0, s, a);
+    } else if constexpr (KOM == KO_OFF) {  // ablation shapes: without dissipation only
+      if (a.ltx == 64)
+        hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 64, 4, 5, KOM>), grid, dim3(nt), 0, s, a);
+      else if (a.ltx == 8)
+        hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 8, 8, 5, KOM>), grid, dim3(nt), 0, s, a);
+      else if (a.lty == 4)
+        hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 4, 5, KOM>), grid, dim3(nt), 0, s, a);
+      else
+        hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 8, 6, KOM>), grid, dim3(nt), 0, s, a);
+    }
   } else if (a.ltx == 32) {
-    hipLaunchKernelGGL((bssn_lds_kernel<STAGE, T, 32, 8>), grid, dim3(256), 0, s, a);
-  } else {
-    hipLaunchKernelGGL((bssn_lds_kernel<STAGE, T, 16, 16>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((bssn_lds_kernel<STAGE, T, 32, 8, KOM>), grid, dim3(256), 0, s, a);
+  } else if (a.ltx == 16) {
+    hipLaunchKernelGGL((bssn_lds_kernel<STAGE, T, 16, 16, KOM>), grid, dim3(256), 0, s, a);
+  } else if constexpr (KOM == KO_OFF) {
+    hipLaunchKernelGGL((bssn_lds_kernel<STAGE, T, 64, 4, KOM>), grid, dim3(256), 0, s, a);
   }
+}
+
+// dissipation on or off: separate instances, so that the default kernels
+// keep their register budget
+template <int STAGE, typename T>
+void launch_shape(const BssnArgs& a, dim3 grid, hipStream_t s) {
+  if (a.P.ko_sigma != 0.0)
+    launch_shape_k<STAGE, T, KO_ON>(a, grid, s);
+  else
+    launch_shape_k<STAGE, T, KO_OFF>(a, grid, s);
 }
 
 template <typename T>
@@ -220,12 +232,15 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
   BssnArgs a;
   a.G = G;
   a.P = P;
-  a.W = make_weights(P.h);
+  a.W = make_weights(P.h, P.ko_sigma);
   a.io = io;
   a.images = images ? 1 : 0;
   a.ltx = G.n[0] >= 24 ? 32 : 16;
   a.lty = 256 / a.ltx;
-  if (kernel_variant(precision) != 0 && forced_tile().w) {
+  // with dissipation only the default tiles exist (forced tiles are an
+  // ablation of the dissipation-free kernels)
+  if (P.ko_sigma != 0.0) {
+  } else if (kernel_variant(precision) != 0 && forced_tile().w) {
     a.ltx = forced_tile().w;
     a.lty = forced_tile().h;
   } else if (forced_tile().w && forced_tile().w * forced_tile().h == 256) {

@@ -72,13 +72,15 @@ struct Weights {
   double i12h[3];   // 1 / (12 h_d)
   double i12hh[3];  // 1 / (12 h_d^2)
   double i144[3];   // 1 / (144 h_a h_b) for (x,y), (x,z), (y,z)
+  double ko[3];     // Kreiss-Oliger: sigma / (64 h_d), all 0 when off
 };
 
-inline Weights make_weights(const double h[3]) {
+inline Weights make_weights(const double h[3], double ko_sigma = 0.0) {
   Weights w;
   for (int d = 0; d < 3; ++d) {
     w.i12h[d] = 1.0 / (12.0 * h[d]);
     w.i12hh[d] = 1.0 / (12.0 * h[d] * h[d]);
+    w.ko[d] = ko_sigma / (64.0 * h[d]);
   }
   w.i144[0] = 1.0 / (144.0 * h[0] * h[1]);
   w.i144[1] = 1.0 / (144.0 * h[0] * h[2]);
@@ -118,7 +120,11 @@ struct GSrc {
 // Centred first derivatives (D1), pure second derivatives (D2) and the
 // advection term beta^k d_k f with the lopsided stencil on the upwind side
 // (ADV) of one grid function.
-template <typename T, bool D1, bool D2, bool ADV, typename Acc>
+// KOM: Kreiss-Oliger mode of the advected variables: 0 off, 1 on, 2 decided
+// at run time (w.ko != 0), for kernels that keep one instance for both.
+enum : int { KO_OFF = 0, KO_ON = 1, KO_RUNTIME = 2 };
+
+template <typename T, bool D1, bool D2, bool ADV, int KOM, typename Acc>
 __device__ __forceinline__ void axis_derivs(const Acc& f, const Weights& w, const bool bpos[3],
                                             const T beta[3], T d1[3], T d2[3], T& adv) {
   const double f0 = f(0, 0, 0);
@@ -140,6 +146,21 @@ __device__ __forceinline__ void axis_derivs(const Acc& f, const Weights& w, cons
       l = up ? l : -l;
       adv += beta[d] * l;
     }
+  }
+  // Kreiss-Oliger dissipation rides on the advection term (every evolved
+  // variable has one): sigma/64 sum_d delta6_d f / h_d, the sixth difference
+  // on neighbour differences.
+  if (ADV && (KOM == KO_ON || (KOM == KO_RUNTIME && w.ko[0] != 0.0))) {
+    T ko = (T)0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int ex = d == 0, ey = d == 1, ez = d == 2;
+      const double s1 = (f(ex, ey, ez) - f0) + (f(-ex, -ey, -ez) - f0);
+      const double s2 = (f(2 * ex, 2 * ey, 2 * ez) - f0) + (f(-2 * ex, -2 * ey, -2 * ez) - f0);
+      const double s3 = (f(3 * ex, 3 * ey, 3 * ez) - f0) + (f(-3 * ex, -3 * ey, -3 * ez) - f0);
+      ko += (((T)s3 - (T)6 * (T)s2) + (T)15 * (T)s1) * (T)w.ko[d];
+    }
+    adv += ko;
   }
   if (CHEMORA_BSSN_FENCE >= 2 || (CHEMORA_BSSN_FENCE == 1 && !D2)) {
     if (D1) {
@@ -200,7 +221,7 @@ __device__ __forceinline__ void second_derivs(const Acc& f, const Weights& w, co
 // conformal metric gu, Christoffels cdu (Gt^i_jk) and their contraction Gd,
 // d_i chi, and the Ricci tensor R_ij (conformal part + chi part).  With ADV
 // the advection terms of gt_ij, Gamt^i and chi are written to rhs as well.
-template <typename T, bool ADV, typename Src>
+template <typename T, bool ADV, int KOM, typename Src>
 __device__ __forceinline__ void bssn_geometry(Src& src, const Weights& w, const bool bpos[3],
                                               const T beta[3], T chi, const T gt[6], T gu[6],
                                               T cdu[3][6], T Gd[3], T dchi[3], T R[6],
@@ -230,7 +251,7 @@ __device__ __forceinline__ void bssn_geometry(Src& src, const Weights& w, const 
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const auto f = src.acquire(V_GT + q);
-    axis_derivs<T, true, true, ADV>(f, w, bpos, beta, dgt[q], dpure, adv);
+    axis_derivs<T, true, true, ADV, KOM>(f, w, bpos, beta, dgt[q], dpure, adv);
     if (ADV) rhs[V_GT + q] = adv;
     second_derivs<T>(f, w, dpure, dd);
     R[q] = (T)(-0.5) * (gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
@@ -264,7 +285,7 @@ __device__ __forceinline__ void bssn_geometry(Src& src, const Weights& w, const 
     T dG[3][3];  // dG[k][j] = d_j Gt^k
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      axis_derivs<T, true, false, ADV>(src.acquire(V_GAM + k), w, bpos, beta, dG[k], dpure, adv);
+      axis_derivs<T, true, false, ADV, KOM>(src.acquire(V_GAM + k), w, bpos, beta, dG[k], dpure, adv);
       if (ADV) rhs[V_GAM + k] = adv;
     }
 #pragma unroll
@@ -306,7 +327,7 @@ __device__ __forceinline__ void bssn_geometry(Src& src, const Weights& w, const 
   // ---- chi: D_i D_j chi = d_i d_j chi - Gt^k_ij d_k chi; chi part of R_ij
   {
     const auto f = src.acquire(V_CHI);
-    axis_derivs<T, true, true, ADV>(f, w, bpos, beta, dchi, dpure, adv);
+    axis_derivs<T, true, true, ADV, KOM>(f, w, bpos, beta, dchi, dpure, adv);
     if (ADV) rhs[V_CHI] = adv;
     second_derivs<T>(f, w, dpure, dd);
 #pragma unroll
@@ -339,7 +360,7 @@ __device__ constexpr int kRhsOrder[V_N] = {
     V_AT + 1, V_AT + 2, V_AT + 3, V_AT + 4, V_AT + 5, V_B + 0, V_B + 1, V_B + 2};
 
 // Right-hand side of all 24 variables at one point, reading through src.
-template <typename T, typename Src>
+template <typename T, int KOM, typename Src>
 __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const BssnPar& P,
                                                T rhs[V_N]) {
   // ---- centre values, upwind sides
@@ -362,7 +383,7 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
   }
 
   T gu[6], cdu[3][6], Gd[3], dchi[3], R[6];
-  bssn_geometry<T, true>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, rhs);
+  bssn_geometry<T, true, KOM>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, rhs);
   T dd[6], dpure[3], d1v[3], adv;
 
   // ---- lapse: D_i D_j alpha with the physical Christoffels
@@ -372,7 +393,7 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
   T X[6];
   {
     const auto f = src.acquire(V_ALP);
-    axis_derivs<T, true, true, true>(f, w, bpos, beta, dalp, dpure, adv);
+    axis_derivs<T, true, true, true, KOM>(f, w, bpos, beta, dalp, dpure, adv);
     rhs[V_ALP] = adv;
     second_derivs<T>(f, w, dpure, dd);
     const T i2chi = (T)0.5 / chi;
@@ -458,7 +479,7 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const auto f = src.acquire(V_BETA + k);
-    axis_derivs<T, true, true, true>(f, w, bpos, beta, dbeta[k], dpure, adv);
+    axis_derivs<T, true, true, true, KOM>(f, w, bpos, beta, dbeta[k], dpure, adv);
     rhs[V_BETA + k] = adv;
     second_derivs<T>(f, w, dpure, dd);
     lapb[k] = gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
@@ -499,7 +520,7 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
   // ---- trK (first derivatives + advection), At and B (advection only)
   {
     T dK[3];
-    axis_derivs<T, true, false, true>(src.acquire(V_TRK), w, bpos, beta, dK, dpure, adv);
+    axis_derivs<T, true, false, true, KOM>(src.acquire(V_TRK), w, bpos, beta, dK, dpure, adv);
     rhs[V_TRK] = adv + rK;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -509,12 +530,12 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
   }
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    axis_derivs<T, false, false, true>(src.acquire(V_AT + q), w, bpos, beta, d1v, dpure, adv);
+    axis_derivs<T, false, false, true, KOM>(src.acquire(V_AT + q), w, bpos, beta, d1v, dpure, adv);
     rhs[V_AT + q] = adv + rA[q];
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    axis_derivs<T, false, false, true>(src.acquire(V_B + q), w, bpos, beta, d1v, dpure, adv);
+    axis_derivs<T, false, false, true, KOM>(src.acquire(V_B + q), w, bpos, beta, d1v, dpure, adv);
     rhs[V_B + q] = adv;
   }
 
@@ -563,9 +584,40 @@ __device__ __forceinline__ double ld_stream(const double* p) {
 #endif
 }
 
+// Algebraic constraints of the conformal variables at one point: rescale
+// gt_ij by det(gt)^(-1/3) so that its determinant is 1, then remove the
+// trace of At_ij with respect to the rescaled metric (inverse = adjugate /
+// determinant): At_ij -= gt_ij gt^kl At_kl / 3.  FP64, on the stage output.
+__device__ __forceinline__ double det3(const double g[6]) {
+  return g[0] * (g[3] * g[5] - g[4] * g[4]) - g[1] * (g[1] * g[5] - g[4] * g[2]) +
+         g[2] * (g[1] * g[4] - g[3] * g[2]);
+}
+__device__ __forceinline__ void enforce_point(double u[V_N]) {
+  double g[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) g[q] = u[V_GT + q];
+  const double sc = 1.0 / cbrt(det3(g));
+#pragma unroll
+  for (int q = 0; q < 6; ++q) g[q] *= sc;
+  const double id = 1.0 / det3(g);
+  // adjugate of the symmetric metric, (xx, xy, xz, yy, yz, zz)
+  const double a[6] = {g[3] * g[5] - g[4] * g[4], g[2] * g[4] - g[1] * g[5],
+                       g[1] * g[4] - g[2] * g[3], g[0] * g[5] - g[2] * g[2],
+                       g[1] * g[2] - g[0] * g[4], g[0] * g[3] - g[1] * g[1]};
+  const double tr = (a[0] * u[V_AT + 0] + a[3] * u[V_AT + 3] + a[5] * u[V_AT + 5] +
+                     2.0 * (a[1] * u[V_AT + 1] + a[2] * u[V_AT + 2] + a[4] * u[V_AT + 4])) *
+                    id;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    u[V_GT + q] = g[q];
+    u[V_AT + q] -= g[q] * tr / 3.0;
+  }
+}
+
 template <int STAGE, typename T>
 __device__ __forceinline__ void bssn_store(const StageIO& io, const Geo& G, long long p, int i,
-                                           int j, int k, const T rhs[V_N], bool images) {
+                                           int j, int k, const T rhs[V_N], bool images,
+                                           bool enforce) {
   double* out = io.out + G.off0;
   if (STAGE == 0) {
 #pragma unroll
@@ -579,24 +631,28 @@ __device__ __forceinline__ void bssn_store(const StageIO& io, const Geo& G, long
     ac[v] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? ld_stream(io.acc + G.off0 + p + v * G.sv)
                                                       : 0.0;
   }
+  double nv[V_N];
 #pragma unroll
   for (int v = 0; v < V_N; ++v) {
     const long long q = p + v * G.sv;
     const double kv = (double)rhs[v];
-    double nv;
     if (STAGE == 1) {
       st_stream(io.acc + G.off0 + q, kv);
-      nv = y0[v] + io.cdt * kv;
+      nv[v] = y0[v] + io.cdt * kv;
     } else if (STAGE == 2 || STAGE == 3) {
       st_stream(io.acc + G.off0 + q, ac[v] + 2.0 * kv);
-      nv = y0[v] + io.cdt * kv;
+      nv[v] = y0[v] + io.cdt * kv;
     } else {
-      nv = y0[v] + io.cdt * (ac[v] + kv);
+      nv[v] = y0[v] + io.cdt * (ac[v] + kv);
     }
+  }
+  if (enforce) enforce_point(nv);
+#pragma unroll
+  for (int v = 0; v < V_N; ++v) {
     if (images) {
-      store_with_images(out + v * G.sv, G, i, j, k, nv, true);
+      store_with_images(out + v * G.sv, G, i, j, k, nv[v], true);
     } else {
-      st_stream(out + q, nv);
+      st_stream(out + p + v * G.sv, nv[v]);
     }
   }
 }

@@ -37,7 +37,7 @@ __device__ __forceinline__ void constraints_point(const double* __restrict__ Y, 
     At[q] = F(V_AT + q)[0];
   }
   double gu[6], cdu[3][6], Gd[3], dchi[3], R[6], unused[V_N];
-  bssn_geometry<double, false>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, unused);
+  bssn_geometry<double, false, KO_OFF>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, unused);
   const double Rsc = chi * (gu[0] * R[0] + gu[3] * R[3] + gu[5] * R[5] +
                             2.0 * (gu[1] * R[1] + gu[2] * R[2] + gu[4] * R[4]));
   double Atm[3][3], Atu[6];
@@ -61,10 +61,10 @@ __device__ __forceinline__ void constraints_point(const double* __restrict__ Y, 
   c[0] = Rsc + (2.0 / 3.0) * trK * trK - AtAt;
 
   double dpure[3], adv, dK[3], dAt[6][3];
-  axis_derivs<double, true, false, false>(src.acquire(V_TRK), w, bpos, beta, dK, dpure, adv);
+  axis_derivs<double, true, false, false, KO_OFF>(src.acquire(V_TRK), w, bpos, beta, dK, dpure, adv);
 #pragma unroll
   for (int q = 0; q < 6; ++q)
-    axis_derivs<double, true, false, false>(src.acquire(V_AT + q), w, bpos, beta, dAt[q], dpure,
+    axis_derivs<double, true, false, false, KO_OFF>(src.acquire(V_AT + q), w, bpos, beta, dAt[q], dpure,
                                             adv);
   // DA[j][ab] = D_j At_ab (conformal covariant derivative)
   double DA[3][6];

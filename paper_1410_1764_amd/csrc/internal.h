@@ -31,6 +31,8 @@ struct BssnPar {
   double F, eta;
   double gw_A, gw_d;
   int gw_axis;
+  int enforce;      // det gt = 1, tr At = 0 after every RK substage
+  double ko_sigma;  // Kreiss-Oliger dissipation strength (0: none)
 };
 
 // The four classical RK4 substages fused with the right-hand side.  Stage 0

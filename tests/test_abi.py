@@ -39,7 +39,11 @@ def _create(**kw):
     (dict(boundary=C.BC_GAUGEWAVE, gw_wavelength=0.0), "wavelength"),
     (dict(slicing=5), "slicing"),
     (dict(shift=5), "shift"),
-    (dict(reserved=1), "reserved"),
+    (dict(enforce=2), "enforce"),
+    (dict(ko_sigma=-0.1), "ko_sigma"),
+    (dict(ko_sigma=float("inf")), "ko_sigma"),
+    (dict(system=C.WAVE, ghost=2, ko_sigma=0.1), "BSSN system only"),
+    (dict(system=C.WAVE, ghost=2, enforce=1), "BSSN system only"),
 ])
 def test_grid_create_rejects(kw, msg):
     with pytest.raises(C.ChemoraError) as e:
