@@ -36,8 +36,8 @@ BSSN_BYTES_PER_PT = 24 * 8 * 2       # read every variable once, write every rhs
 # paper_1410_1764_amd/kernel_facts.json; the same file holds the HBM traffic
 # per launch measured with hardware counters, valid only while the hash of
 # the kernel sources matches.
-KERNEL_FP64 = "bssn_async_kernel<0,double,32,8,6>"
-KERNEL_MIXED = "bssn_lds_kernel<0,float,32,8>"
+KERNEL_FP64 = "bssn_async_kernel<0,double,32,8,6,KO_OFF>"
+KERNEL_MIXED = "bssn_lds_kernel<0,float,32,8,KO_OFF>"
 # Mixed precision runs unpacked FP32 (packed FP32 is disabled at compile
 # time), which issues at the FP64 vector rate: 256 CUs x 4 SIMDs x 16 lanes
 # x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s.
