@@ -171,7 +171,7 @@ __device__ __forceinline__ void wait_vm_lgkm0() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (0 << 8) | (((N >> 4) & 3) << 14));
 }
 
-template <int TX, int TY, int NBUF>
+template <int TX, int TY, int NBUF, typename ORDER = RhsOrder>
 struct ASrc {
   using S = LdsShape<TX, TY>;
   static constexpr int PAIRS = S::TOTAL / 2;
@@ -232,9 +232,9 @@ struct ASrc {
     seq = 0;
   }
 
-  // start copying grid function kRhsOrder[s] into buffer s % NBUF
+  // start copying grid function ORDER::at(s) into buffer s % NBUF
   __device__ __forceinline__ void issue(int s) {
-    const char* base = Yb + (long long)kRhsOrder[s] * sv * 8;
+    const char* base = Yb + (long long)ORDER::at(s) * sv * 8;
     double* dst = buf[s % NBUF];
     const int lane = (int)threadIdx.x & 63;
 #pragma unroll
@@ -267,7 +267,7 @@ struct ASrc {
 #pragma unroll
       for (int s = 0; s < D; ++s) issue(s);
     }
-    const int last = seq + D - 1 < V_N - 1 ? seq + D - 1 : V_N - 1;
+    const int last = seq + D - 1 < ORDER::N - 1 ? seq + D - 1 : ORDER::N - 1;
     switch (last - seq) {  // folds to one case once seq is known
       case 0: wait_and_sync<0>(); break;
       case 1: wait_and_sync<1>(); break;
@@ -276,7 +276,7 @@ struct ASrc {
       case 4: wait_and_sync<4>(); break;
       default: wait_and_sync<5>(); break;
     }
-    if (seq + D < V_N) issue(seq + D);
+    if (seq + D < ORDER::N) issue(seq + D);
     double* b = buf[seq % NBUF];
     ++seq;
     return LAcc<TX, TY>{b + b0o, b + b1o, b + b3o};

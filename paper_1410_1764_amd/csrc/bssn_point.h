@@ -359,6 +359,22 @@ __device__ constexpr int kRhsOrder[V_N] = {
     V_GAM + 2, V_CHI, V_ALP, V_BETA + 0, V_BETA + 1, V_BETA + 2, V_TRK, V_AT + 0,
     V_AT + 1, V_AT + 2, V_AT + 3, V_AT + 4, V_AT + 5, V_B + 0, V_B + 1, V_B + 2};
 
+// Acquisition orders, as types for the staging sources: the right-hand
+// side acquires all 24 grid functions (kRhsOrder); the constraints acquire
+// the ones the geometry needs (gt, Gamt, chi), then K and At.
+struct RhsOrder {
+  static constexpr int N = V_N;
+  __device__ static constexpr int at(int s) { return kRhsOrder[s]; }
+};
+__device__ constexpr int kConsOrder[17] = {V_GT + 0, V_GT + 1, V_GT + 2, V_GT + 3, V_GT + 4,
+                                           V_GT + 5, V_GAM + 0, V_GAM + 1, V_GAM + 2, V_CHI,
+                                           V_TRK, V_AT + 0, V_AT + 1, V_AT + 2, V_AT + 3,
+                                           V_AT + 4, V_AT + 5};
+struct ConsOrder {
+  static constexpr int N = 17;
+  __device__ static constexpr int at(int s) { return kConsOrder[s]; }
+};
+
 // Right-hand side of all 24 variables at one point, reading through src.
 template <typename T, int KOM, typename Src>
 __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const BssnPar& P,

@@ -5,7 +5,10 @@
 //   H   = R + 2/3 K^2 - At^ij At_ij,   R = chi gt^ij R_ij
 //   M^i = gt^ia gt^jb (d_j At_ab - Gt^m_ja At_mb - Gt^m_jb At_am)
 //         - 2/3 gt^ij d_j K - 3/2 At^ij d_j chi / chi
-#include "bssn_point.h"
+#include <cstdlib>
+#include <cstring>
+
+#include "bssn_lds.h"
 
 namespace chemora {
 namespace {
@@ -20,21 +23,21 @@ struct ConsArgs {
   double* partial;  // 4 doubles per workgroup
   int ltx, lty, zc;
   int tiles[3];
+  int cols[2];  // staged kernel: column split of the tile grid (0: XCD-contiguous order)
 };
 
-__device__ __forceinline__ void constraints_point(const double* __restrict__ Y, long long sv,
-                                                  const long long st[3], const Weights& w,
-                                                  double c[4]) {
-  GSrc src{Y, sv, st[1], st[2]};
-  auto F = [&](int v) { return Y + v * sv; };
+// H and M^i at one point, reading through a neighbourhood source (GSrc or
+// the LDS-staged ASrc with the constraints' acquisition order)
+template <typename Src>
+__device__ __forceinline__ void constraints_point(Src& src, const Weights& w, double c[4]) {
   const bool bpos[3] = {true, true, true};
   const double beta[3] = {0.0, 0.0, 0.0};
-  const double chi = F(V_CHI)[0], trK = F(V_TRK)[0];
+  const double chi = src.center(V_CHI), trK = src.center(V_TRK);
   double gt[6], At[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    gt[q] = F(V_GT + q)[0];
-    At[q] = F(V_AT + q)[0];
+    gt[q] = src.center(V_GT + q);
+    At[q] = src.center(V_AT + q);
   }
   double gu[6], cdu[3][6], Gd[3], dchi[3], R[6], unused[V_N];
   bssn_geometry<double, false, KO_OFF>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, unused);
@@ -116,7 +119,8 @@ __global__ void __launch_bounds__(CT) constraints_kernel(ConsArgs a) {
     for (int k = k0; k < k1; ++k) {
       const long long p = i + (long long)j * G.sy + (long long)k * G.sz;
       double c[4];
-      constraints_point(a.y + G.off0 + p, G.sv, st, a.W, c);
+      GSrc src{a.y + G.off0 + p, G.sv, st[1], st[2]};
+      constraints_point(src, a.W, c);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         sum[q] += c[q] * c[q];
@@ -134,6 +138,58 @@ __global__ void __launch_bounds__(CT) constraints_kernel(ConsArgs a) {
     __syncthreads();
   }
   if (threadIdx.x < 4) a.partial[4LL * b + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// LDS-staged variant (the right-hand side's async staging with the
+// constraints' 17 grid functions): one plane of a TX x TY tile per
+// workgroup, tiles in the XCD column walk; workgroup b writes partial b
+// (zeros when the column walk gives it no tile).
+template <int TX, int TY, int NBUF>
+__global__ void __launch_bounds__(TX * TY) constraints_async_kernel(ConsArgs a) {
+  using S = LdsShape<TX, TY>;
+  constexpr int NT = TX * TY;
+  __shared__ double L0[S::TOTAL], L1[S::TOTAL], L2[S::TOTAL], L3[S::TOTAL], L4[S::TOTAL],
+      L5[S::TOTAL];
+  __shared__ double red[4][NT];
+  double* const bufs[6] = {L0, L1, L2, L3, L4, L5};
+  const Geo& G = a.G;
+  int bx, by, k;
+  bool has;
+  if (a.cols[0] > 0) {
+    has = column_tile(blockIdx.x, a.tiles, a.cols[0], a.cols[1], bx, by, k);
+  } else {
+    const int t = xcd_tile(blockIdx.x, a.tiles[0] * a.tiles[1] * a.tiles[2]);
+    bx = t % a.tiles[0];
+    by = (t / a.tiles[0]) % a.tiles[1];
+    k = t / (a.tiles[0] * a.tiles[1]);
+    has = true;
+  }
+  if (!has) {  // whole workgroup, before any barrier
+    if (threadIdx.x < 4) a.partial[4LL * blockIdx.x + threadIdx.x] = 0.0;
+    return;
+  }
+  const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
+  const int x0 = bx * TX, y0 = by * TY;
+  const int i = x0 + tx, j = y0 + ty;
+  const bool active = i < G.n[0] && j < G.n[1];
+  ASrc<TX, TY, NBUF, ConsOrder> src;
+  src.init(G, a.y, bufs, x0, y0, k, tx, ty);
+  double c[4];
+  constraints_point(src, a.W, c);
+  const long long p = i + (long long)j * G.sy + (long long)k * G.sz;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (a.hm && active) a.hm[G.off0 + p + q * G.sv] = c[q];
+    red[q][threadIdx.x] = active ? c[q] * c[q] : 0.0;
+  }
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) a.partial[4LL * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Sum the per-workgroup partials in a fixed order and take sqrt(sum / N).
@@ -156,7 +212,43 @@ __global__ void __launch_bounds__(CT) norms_kernel(const double* partial, int nb
   if (threadIdx.x < 4) norms[threadIdx.x] = sqrt(red[threadIdx.x][0] / npts);
 }
 
-void plan(const Geo& G, ConsArgs& a) {
+// CHEMORA_CONS_NBUF=3|6: staging buffers of the staged kernel (3: two
+// workgroups fit a CU; ablation switch)
+int cons_nbuf() {
+  static const int v = [] {
+    const char* e = std::getenv("CHEMORA_CONS_NBUF");
+    return (e && std::atoi(e) == 6) ? 6 : 3;
+  }();
+  return v;
+}
+
+// CHEMORA_CONS_KERNEL=global selects the cached-load kernel (ablation switch)
+bool staged() {
+  static const bool v = [] {
+    const char* e = std::getenv("CHEMORA_CONS_KERNEL");
+    return !(e && std::strcmp(e, "global") == 0);
+  }();
+  return v;
+}
+
+// returns the number of workgroups
+long long plan(const Geo& G, ConsArgs& a) {
+  a.cols[0] = a.cols[1] = 0;
+  if (staged()) {
+    a.ltx = G.n[0] >= 24 ? 32 : 16;
+    a.lty = CT / a.ltx;
+    a.tiles[0] = (G.n[0] + a.ltx - 1) / a.ltx;
+    a.tiles[1] = (G.n[1] + a.lty - 1) / a.lty;
+    a.zc = 1;
+    a.tiles[2] = G.n[2];
+    const ColumnSplit c = column_split(a.tiles, a.ltx, a.lty);
+    if (c.cx > 0) {
+      a.cols[0] = c.cx;
+      a.cols[1] = c.cy;
+      return c.blocks_per_plane * a.tiles[2];
+    }
+    return (long long)a.tiles[0] * a.tiles[1] * a.tiles[2];
+  }
   a.ltx = G.n[0] >= 48 ? 64 : (G.n[0] >= 24 ? 32 : 16);
   a.lty = CT / a.ltx;
   a.tiles[0] = (G.n[0] + a.ltx - 1) / a.ltx;
@@ -167,14 +259,14 @@ void plan(const Geo& G, ConsArgs& a) {
   if (zsplit < 1) zsplit = 1;
   a.zc = (G.n[2] + zsplit - 1) / zsplit;
   a.tiles[2] = (G.n[2] + a.zc - 1) / a.zc;
+  return (long long)a.tiles[0] * a.tiles[1] * a.tiles[2];
 }
 
 }  // namespace
 
 long long constraints_partial_count(const Geo& G) {
   ConsArgs a;
-  plan(G, a);
-  return 4LL * a.tiles[0] * a.tiles[1] * a.tiles[2];
+  return 4LL * plan(G, a);
 }
 
 hipError_t launch_bssn_constraints(const Geo& G, const BssnPar& P, const double* y, double* hm,
@@ -185,9 +277,15 @@ hipError_t launch_bssn_constraints(const Geo& G, const BssnPar& P, const double*
   a.y = y;
   a.hm = hm;
   a.partial = partial;
-  plan(G, a);
-  const int nb = a.tiles[0] * a.tiles[1] * a.tiles[2];
-  hipLaunchKernelGGL(constraints_kernel, dim3(nb), dim3(CT), 0, s, a);
+  const int nb = (int)plan(G, a);
+  if (!staged())
+    hipLaunchKernelGGL(constraints_kernel, dim3(nb), dim3(CT), 0, s, a);
+  else if (a.ltx == 32 && cons_nbuf() == 6)
+    hipLaunchKernelGGL((constraints_async_kernel<32, 8, 6>), dim3(nb), dim3(CT), 0, s, a);
+  else if (a.ltx == 32)
+    hipLaunchKernelGGL((constraints_async_kernel<32, 8, 3>), dim3(nb), dim3(CT), 0, s, a);
+  else
+    hipLaunchKernelGGL((constraints_async_kernel<16, 16, 3>), dim3(nb), dim3(CT), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double npts = (double)G.n[0] * G.n[1] * G.n[2];

@@ -137,8 +137,10 @@ def test_bssn_rk4_parity(bc, gauge):
     assert eg <= TOL_FP64
 
 
-def test_constraints_parity():
-    n = (22, 18, 14)
+@pytest.mark.parametrize("n", [(22, 18, 14), (37, 21, 13), (70, 40, 9)])
+def test_constraints_parity(n):
+    # 16 x 16 tiles; 32 x 8 tiles without a column split; 32 x 8 tiles in
+    # uneven XCD columns (some workgroups get no tile)
     h = tuple(1.0 / v for v in n)
     gr, b = pair(n, 3, h, C.BSSN)
     y0 = _smooth_random(n, 9)
