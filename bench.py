@@ -75,6 +75,8 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-patch batch timing")
+    ap.add_argument("--only-wave", action="store_true",
+                    help="time only the 256^3 wave RK4 steps and the copy (for profiler runs)")
     ap.add_argument("--only-rhs", action="store_true",
                     help="time only the FP64 right-hand side (for profiler runs)")
     args = ap.parse_args(argv)
@@ -90,6 +92,20 @@ def main(argv=None) -> int:
     from paper_1410_1764_amd import inputs as I
 
     torch.cuda.set_device(0)
+    if args.only_wave:
+        nw = 256
+        hw = 1.0 / nw
+        gw64 = C.Grid((nw, nw, nw), 2, hw, system=C.WAVE, precision=C.FP64)
+        sw = gw64.upload(I.fourier_modes(nw, 16, I.SEED0 + 1))
+        wsw = gw64.new_workspace()
+        gw64.rk4_step(sw, wsw, 0.0, 0.25 * hw, 2)
+        kw64 = _events_time(lambda: gw64.rk4_step(sw, wsw, 0.0, 0.25 * hw, 5), 1) / 5
+        nb = 1 << 29
+        a = torch.empty(nb // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        kc = _events_time(lambda: C.probe_copy(b, a, nb), 2)
+        print(json.dumps({"wave256_rk4_step_fp64_ms": kw64 * 1e3, "copy_512MiB_ms": kc * 1e3}))
+        return 0
     n = args.n
     h = 1.0 / n
     y0 = I.gaugewave((n, n, n), h, A=0.1, d=1.0, axis=0)

@@ -5,11 +5,29 @@
 namespace chemora {
 namespace {
 
-__global__ void __launch_bounds__(256) copy_kernel(double2* __restrict__ dst,
-                                                   const double2* __restrict__ src, long long n) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride)
-    dst[t] = src[t];
+// Each workgroup copies contiguous chunks of 4 x 256 16-byte elements with
+// all four loads of a thread in flight before its stores (a grid-stride
+// loop with one element per step measured ~10 % lower bandwidth).
+typedef double d2v __attribute__((ext_vector_type(2)));
+constexpr int kUnroll = 4;
+
+__global__ void __launch_bounds__(256) copy_kernel(d2v* __restrict__ dst,
+                                                   const d2v* __restrict__ src, long long n) {
+  const long long chunk = (long long)kUnroll * 256;
+  for (long long base = (long long)blockIdx.x * chunk; base < n;
+       base += (long long)gridDim.x * chunk) {
+    d2v v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const long long t = base + u * 256 + threadIdx.x;
+      if (t < n) v[u] = src[t];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const long long t = base + u * 256 + threadIdx.x;
+      if (t < n) dst[t] = v[u];
+    }
+  }
 }
 
 }  // namespace
@@ -17,10 +35,10 @@ __global__ void __launch_bounds__(256) copy_kernel(double2* __restrict__ dst,
 hipError_t launch_probe_copy(void* dst, const void* src, long long nbytes, hipStream_t s) {
   const long long n = nbytes / 16;
   if (n == 0) return hipSuccess;
-  long long blocks = (n + 255) / 256;
-  if (blocks > 256 * 32) blocks = 256 * 32;
+  long long blocks = (n + kUnroll * 256 - 1) / (kUnroll * 256);
+  if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
-                     static_cast<double2*>(dst), static_cast<const double2*>(src), n);
+                     static_cast<d2v*>(dst), static_cast<const d2v*>(src), n);
   return hipGetLastError();
 }
 

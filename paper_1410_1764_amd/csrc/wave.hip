@@ -13,6 +13,8 @@
 // The differences are always formed in double; the weights and the sum are
 // done in T (double, or float for the mixed path).  The stage update is
 // always double.
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace chemora {
@@ -29,6 +31,42 @@ struct WaveArgs {
   int images;    // write periodic images of the stage output
 };
 
+// Barrier between the LDS tile's writes and reads: the tile only needs the
+// LDS writes done (lgkmcnt(0)); __syncthreads() would also wait for every
+// global access in flight, including the next plane's prefetched operands.
+// The empty asm statements keep the compiler from moving memory accesses
+// across it.
+__device__ __forceinline__ void tile_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt((15) | (7 << 4) | (0 << 8) | (3 << 14));  // lgkmcnt(0) only
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Pointwise operands of one plane: rho at the point, and for the substage
+// update y_n (u, rho) and the accumulator (u, rho).
+struct Pointwise {
+  double rho, u0, r0, au, ar;
+};
+
+template <int STAGE>
+__device__ __forceinline__ Pointwise load_pointwise(const WaveArgs& a, long long p) {
+  const Geo& G = a.G;
+  Pointwise w;
+  w.rho = a.io.yin[G.off0 + p + G.sv];
+  w.u0 = w.r0 = w.au = w.ar = 0.0;
+  if (STAGE >= 2) {
+    w.u0 = a.io.y0[G.off0 + p];
+    w.r0 = a.io.y0[G.off0 + p + G.sv];
+    w.au = a.io.acc[G.off0 + p];
+    w.ar = a.io.acc[G.off0 + p + G.sv];
+  }
+  return w;
+}
+
+// The z-march is software-pipelined: a plane's pointwise operands are
+// loaded during the previous plane, before its stores, so that they are in
+// flight across the tile barriers instead of being waited for each plane.
 template <int STAGE, typename T>
 __global__ void __launch_bounds__(TX * TY) wave_stage_kernel(WaveArgs a) {
   __shared__ double tile[TY + 2 * R][TX + 2 * R];
@@ -43,7 +81,6 @@ __global__ void __launch_bounds__(TX * TY) wave_stage_kernel(WaveArgs a) {
   const bool comp = i < G.n[0] && j < G.n[1];
   const bool col_ok = i < G.n[0] + R && j < G.n[1] + R;
   const double* U = a.io.yin + G.off0;
-  const double* RH = U + G.sv;
   const long long col = i + (long long)j * G.sy;
   const long long sz = G.sz;
 
@@ -54,19 +91,21 @@ __global__ void __launch_bounds__(TX * TY) wave_stage_kernel(WaveArgs a) {
     q2 = U[col + k0 * sz];
     q3 = U[col + (k0 + 1) * sz];
   }
+  Pointwise pw{0.0, 0.0, 0.0, 0.0, 0.0};
+  if (comp && k0 < k1) pw = load_pointwise<STAGE>(a, col + k0 * sz);
   const T w2x = (T)a.w2[0], w2y = (T)a.w2[1], w2z = (T)a.w2[2];
 
   for (int k = k0; k < k1; ++k) {
     const long long pk = col + k * sz;
     if (col_ok) q4 = U[pk + 2 * sz];
-    __syncthreads();
+    tile_barrier();
     tile[ty + R][tx + R] = q2;
     if (tx < R && j < G.n[1] + R) tile[ty + R][tx] = U[pk - R];
     if (tx >= TX - R && i < G.n[0] && j < G.n[1] + R) tile[ty + R][tx + 2 * R] = U[pk + R];
     if (ty < R && i < G.n[0] + R) tile[ty][tx + R] = U[pk - (long long)R * G.sy];
     if (ty >= TY - R && j < G.n[1] && i < G.n[0] + R)
       tile[ty + 2 * R][tx + R] = U[pk + (long long)R * G.sy];
-    __syncthreads();
+    tile_barrier();
     if (comp) {
       const double c = q2;
       const double sx1 = (tile[ty + R][tx + R + 1] - c) + (tile[ty + R][tx + R - 1] - c);
@@ -77,8 +116,9 @@ __global__ void __launch_bounds__(TX * TY) wave_stage_kernel(WaveArgs a) {
       const double sz2 = (q4 - c) + (q0 - c);
       const T lap = ((T)16 * (T)sx1 - (T)sx2) * w2x + ((T)16 * (T)sy1 - (T)sy2) * w2y +
                     ((T)16 * (T)sz1 - (T)sz2) * w2z;
-      const double rho = RH[pk];
-      const double ku = rho, kr = (double)lap;
+      const Pointwise cur = pw;
+      if (k + 1 < k1) pw = load_pointwise<STAGE>(a, pk + sz);  // before this plane's stores
+      const double ku = cur.rho, kr = (double)lap;
       const long long p = pk;
       double* out = a.io.out + G.off0;
       if (STAGE == 0) {
@@ -86,17 +126,7 @@ __global__ void __launch_bounds__(TX * TY) wave_stage_kernel(WaveArgs a) {
         out[p + G.sv] = kr;
       } else {
         double* acc = a.io.acc + G.off0;
-        const double* y0 = a.io.y0 + G.off0;
-        double u0, r0, au = 0.0, ar = 0.0;
-        if (STAGE == 1) {
-          u0 = c;
-          r0 = rho;
-        } else {
-          u0 = y0[p];
-          r0 = y0[p + G.sv];
-          au = acc[p];  // loads before the first store
-          ar = acc[p + G.sv];
-        }
+        const double u0 = STAGE == 1 ? c : cur.u0, r0 = STAGE == 1 ? cur.rho : cur.r0;
         double nu, nr;
         if (STAGE == 1) {
           acc[p] = ku;
@@ -104,13 +134,13 @@ __global__ void __launch_bounds__(TX * TY) wave_stage_kernel(WaveArgs a) {
           nu = u0 + a.io.cdt * ku;
           nr = r0 + a.io.cdt * kr;
         } else if (STAGE == 2 || STAGE == 3) {
-          acc[p] = au + 2.0 * ku;
-          acc[p + G.sv] = ar + 2.0 * kr;
+          acc[p] = cur.au + 2.0 * ku;
+          acc[p + G.sv] = cur.ar + 2.0 * kr;
           nu = u0 + a.io.cdt * ku;
           nr = r0 + a.io.cdt * kr;
         } else {
-          nu = u0 + a.io.cdt * (au + ku);
-          nr = r0 + a.io.cdt * (ar + kr);
+          nu = u0 + a.io.cdt * (cur.au + ku);
+          nr = r0 + a.io.cdt * (cur.ar + kr);
         }
         store_with_images(out, G, i, j, k, nu, a.images);
         store_with_images(out + G.sv, G, i, j, k, nr, a.images);
@@ -136,6 +166,16 @@ hipError_t launch_t(int stage, const WaveArgs& a, dim3 grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+// workgroups the z-split aims for (CHEMORA_WAVE_WGS overrides; ablation)
+long long wave_workgroups() {
+  static const long long v = [] {
+    const char* e = std::getenv("CHEMORA_WAVE_WGS");
+    const long long n = e ? std::atoll(e) : 0;
+    return n >= 256 && n <= (1 << 20) ? n : 16384LL;
+  }();
+  return v;
+}
+
 }  // namespace
 
 hipError_t launch_wave_stage(const Geo& G, const double h[3], int stage, int precision,
@@ -147,9 +187,10 @@ hipError_t launch_wave_stage(const Geo& G, const double h[3], int stage, int pre
   a.images = images ? 1 : 0;
   a.tiles[0] = (G.n[0] + TX - 1) / TX;
   a.tiles[1] = (G.n[1] + TY - 1) / TY;
-  // enough workgroups to fill 256 CUs several times over; each marches zc planes
+  // enough workgroups to fill 256 CUs many times over (measured at 256^3: 16384
+  // workgroups of 4 planes, 1.17 ms per RK4 step, against 1.21 ms for 4096 of 16)
   const long long xy = (long long)a.tiles[0] * a.tiles[1];
-  const long long want = 4096;
+  const long long want = wave_workgroups();
   int zsplit = (int)((want + xy - 1) / xy);
   if (zsplit > G.n[2]) zsplit = G.n[2];
   if (zsplit < 1) zsplit = 1;
