@@ -142,11 +142,12 @@ TileShape forced_tile() {
   return t;
 }
 
-// Kernel choice (measured at 128^3): FP64 -> async staging (five grid
-// functions in flight hide the memory latency that one wave per SIMD
-// cannot); mixed -> LDS staging (its 248 VGPRs and 44 KB of LDS allow two
-// waves per SIMD).  CHEMORA_BSSN_KERNEL=global|lds|async overrides it
-// (ablation switch).
+// Kernel choice (measured at 128^3): async staging with three buffers in both
+// precisions (FP64 0.757 ms, mixed 0.584 ms; six buffers: 0.764 / 0.758 ms;
+// register-prefetched LDS staging: 0.766 / 0.641 ms).  Three buffers
+// (66 KB) let two mixed-precision workgroups share a CU, so the mixed
+// kernel (245 VGPRs) runs two waves per SIMD.
+// CHEMORA_BSSN_KERNEL=global|lds|async overrides it (ablation switch).
 int kernel_override() {
   static const int v = [] {
     const char* e = std::getenv("CHEMORA_BSSN_KERNEL");
@@ -159,7 +160,18 @@ int kernel_override() {
 }
 int kernel_variant(int precision) {
   const int o = kernel_override();
-  return o >= 0 ? o : (precision == CHEMORA_MIXED ? 1 : 2);
+  (void)precision;
+  return o >= 0 ? o : 2;
+}
+
+// CHEMORA_BSSN_NBUF=6: six staging buffers for the async 32x8 kernel
+// instead of three (ablation switch)
+int async_nbuf() {
+  static const int v = [] {
+    const char* e = std::getenv("CHEMORA_BSSN_NBUF");
+    return (e && std::atoi(e) == 6) ? 6 : 3;
+  }();
+  return v;
 }
 
 // CHEMORA_BSSN_ORDER=plane restores the XCD-contiguous plane order of the
@@ -180,7 +192,9 @@ void launch_shape_k(const BssnArgs& a, dim3 grid, hipStream_t s) {
   if (variant == 0) {
     hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T, KOM>), grid, dim3(256), 0, s, a);
   } else if (variant == 2) {
-    if (a.ltx == 32) {
+    if (a.ltx == 32 && async_nbuf() == 3) {
+      hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 32, 8, 3, KOM>), grid, dim3(nt), 0, s, a);
+    } else if (a.ltx == 32) {
       hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 32, 8, 6, KOM>), grid, dim3(nt), 0, s, a);
     } else if (a.ltx == 16 && a.lty == 16) {
       hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 16, 16, 6, KOM>), grid, dim3(nt), 0, s, a);

@@ -7,8 +7,8 @@ per grid point (plus a handful of index operations outside the point loop).
 FLOPs: v_fma/v_fmac = 2; add, sub, mul, ldexp (a multiply by a power of two),
 rcp and sqrt = 1; conversions and selects are not counted.
 
-Counts the default kernels (FP64: async-staged 32x8 tiles; mixed: LDS-staged
-32x8 tiles) and writes paper_1410_1764_amd/kernel_facts.json, which bench.py
+Counts the default kernels (async-staged 32x8 tiles, three buffers, no
+dissipation, in FP64 and in mixed precision) and writes paper_1410_1764_amd/kernel_facts.json, which bench.py
 reads for the ALU roofline.  The same file carries the HBM traffic per launch
 measured with hardware counters, keyed by a hash of the kernel sources so that
 a stale figure is not reported once the kernel has changed.
@@ -80,12 +80,12 @@ def main():
     result = {"source": "paper_1410_1764_amd/csrc/bssn.hip", "arch": B.ARCH,
               "command": "python -m paper_1410_1764_amd.isa_count"}
     for name, body in kernel_bodies(asm):
-        if "bssn_async_kernelILi0EdLi32ELi8ELi6E" in name:
+        if "bssn_async_kernelILi0EdLi32ELi8ELi3ELi0E" in name:
             c = count(body)
             result["fp64"] = {"kernel": name, "flops_per_point": c["f64"]["flops_per_point"],
                               "instructions": c["f64"]["instructions"],
                               "global_loads": c["global_load"], "scratch_ops": c["scratch"]}
-        if "bssn_lds_kernelILi0EfLi32ELi8E" in name:
+        if "bssn_async_kernelILi0EfLi32ELi8ELi3ELi0E" in name:
             c = count(body)
             result["mixed"] = {"kernel": name, "f32_flops_per_point": c["f32"]["flops_per_point"],
                                "f64_flops_per_point": c["f64"]["flops_per_point"],
