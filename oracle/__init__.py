@@ -64,7 +64,7 @@ class _Params(ctypes.Structure):
                 ("shift_F", ctypes.c_double), ("eta", ctypes.c_double),
                 ("gw_amp", ctypes.c_double), ("gw_d", ctypes.c_double),
                 ("gw_axis", ctypes.c_int), ("ko_sigma", ctypes.c_double),
-                ("enforce", ctypes.c_int)]
+                ("enforce", ctypes.c_int), ("fd_order", ctypes.c_int)]
 
 
 _lib = None
@@ -117,7 +117,7 @@ class Block:
 
     def __init__(self, n, g, h, origin=(0.0, 0.0, 0.0), slicing=0, shift=1,
                  shift_F=0.75, eta=2.0, gw_amp=0.1, gw_d=1.0, gw_axis=0, ko_sigma=0.0,
-                 enforce=0):
+                 enforce=0, fd_order=4):
         self.n = tuple(int(v) for v in n)
         self.g = int(g)
         self.h = tuple(float(v) for v in (h if np.ndim(h) else (h, h, h)))
@@ -134,6 +134,8 @@ class Block:
         p.gw_amp, p.gw_d, p.gw_axis = self.gw_amp, self.gw_d, self.gw_axis
         self.ko_sigma, self.enforce = float(ko_sigma), int(enforce)
         p.ko_sigma, p.enforce = self.ko_sigma, self.enforce
+        self.fd_order = int(fd_order)
+        p.fd_order = self.fd_order
         self._p = p
 
     @property

@@ -107,9 +107,6 @@ static double fd11(const double* f, long sa, long sb, double ha, double hb) {
   return (64.0 * q[1][1] - 8.0 * q[1][2] - 8.0 * q[2][1] + q[2][2]) / (144.0 * ha * hb);
 }
 
-/* lopsided first derivative, shifted one point towards the upwind side
- * chosen by the sign of the advecting velocity: weights (-3, -10, 18, -6, 1)
- * at offsets (-1, 0, 1, 2, 3) for vel >= 0, mirrored for vel < 0 */
 /* sixth difference along stride s, on neighbour differences:
  * f3 - 6 f2 + 15 f1 - 20 f0 + 15 f-1 - 6 f-2 + f-3
  * = [(f3-f0)+(f-3-f0)] - 6 [(f2-f0)+(f-2-f0)] + 15 [(f1-f0)+(f-1-f0)].
@@ -125,6 +122,9 @@ static double delta6(const double* f, long s) {
   return (s3 - 6.0 * s2) + 15.0 * s1;
 }
 
+/* lopsided first derivative, shifted one point towards the upwind side
+ * chosen by the sign of the advecting velocity: weights (-3, -10, 18, -6, 1)
+ * at offsets (-1, 0, 1, 2, 3) for vel >= 0, mirrored for vel < 0 */
 static double fdup(const double* f, long s, double h, double vel) {
   const double f0 = f[0];
   if (vel >= 0.0)
@@ -134,6 +134,78 @@ static double fdup(const double* f, long s, double h, double vel) {
   return (3.0 * (f[s] - f0) - 18.0 * (f[-s] - f0) + 6.0 * (f[-2 * s] - f0) -
           (f[-3 * s] - f0)) /
          (12.0 * h);
+}
+
+/* Higher orders (the paper's code generator takes the finite-difference
+ * order as a parameter, Sec. III.B.2).  The 4th-order operators above are
+ * used for order 4; orders 6 and 8 use these, the standard centred
+ * operators and the lopsided ones shifted one point upwind, each the unique
+ * stencil on its points that is exact for polynomials of degree <= order,
+ * written on neighbour differences with integer weights over a common
+ * denominator:
+ *   first:  sum_k A_k (f_k - f_-k) / (den h),        k = 1..m (m = order/2)
+ *   second: sum_k B_k ((f_k - f0) + (f_-k - f0)) / (den2 h^2)
+ *   mixed:  sum_(i,j) A_i A_j q_ij / (den^2 h_a h_b), q as for fd11
+ *   upwind: sum_k U_k (f_k - f0) / (den h), k = -(m-1)..m+1, k != 0,
+ *           mirrored (k -> -k, sign flipped) for vel < 0.              */
+typedef struct {
+  int m;                 /* half width of the centred stencils */
+  double A[4], den;      /* first derivative */
+  double B[4], den2;     /* second derivative */
+  double U[10], uden;    /* upwind weights at offsets -(m-1) .. m+1 (index k + m - 1) */
+} fdcoef;
+
+static const fdcoef FD6 = {3, {45, -9, 1, 0}, 60, {270, -27, 2, 0}, 180,
+                           {2, -24, -35, 80, -30, 8, -1, 0, 0, 0}, 60};
+static const fdcoef FD8 = {4, {672, -168, 32, -3}, 840, {8064, -1008, 128, -9}, 5040,
+                           {-5, 60, -420, -378, 1050, -420, 140, -30, 3, 0}, 840};
+
+static const fdcoef* fd_table(int order) { return order == 8 ? &FD8 : &FD6; }
+
+static double fd1o(const fdcoef* c, const double* f, long s, double h) {
+  double acc = 0.0;
+  for (int k = 1; k <= c->m; k++) acc += c->A[k - 1] * (f[k * s] - f[-k * s]);
+  return acc / (c->den * h);
+}
+
+static double fd2o(const fdcoef* c, const double* f, long s, double h) {
+  double acc = 0.0;
+  for (int k = 1; k <= c->m; k++) acc += c->B[k - 1] * ((f[k * s] - f[0]) + (f[-k * s] - f[0]));
+  return acc / (c->den2 * h * h);
+}
+
+static double fd11o(const fdcoef* c, const double* f, long sa, long sb, double ha, double hb) {
+  double acc = 0.0;
+  for (int i = 1; i <= c->m; i++)
+    for (int j = 1; j <= c->m; j++) {
+      const double q = (f[i * sa + j * sb] - f[-i * sa + j * sb]) -
+                       (f[i * sa - j * sb] - f[-i * sa - j * sb]);
+      acc += c->A[i - 1] * c->A[j - 1] * q;
+    }
+  return acc / (c->den * c->den * ha * hb);
+}
+
+static double fdupo(const fdcoef* c, const double* f, long s, double h, double vel) {
+  const long dir = vel >= 0.0 ? s : -s;
+  double acc = 0.0;
+  for (int k = -(c->m - 1); k <= c->m + 1; k++)
+    if (k != 0) acc += c->U[k + c->m - 1] * (f[k * dir] - f[0]);
+  return (vel >= 0.0 ? acc : -acc) / (c->uden * h);
+}
+
+/* order dispatch: 0 or 4 -> the 4th-order operators */
+static double D1(int order, const double* f, long s, double h) {
+  return (order == 6 || order == 8) ? fd1o(fd_table(order), f, s, h) : fd1(f, s, h);
+}
+static double D2(int order, const double* f, long s, double h) {
+  return (order == 6 || order == 8) ? fd2o(fd_table(order), f, s, h) : fd2(f, s, h);
+}
+static double D11(int order, const double* f, long sa, long sb, double ha, double hb) {
+  return (order == 6 || order == 8) ? fd11o(fd_table(order), f, sa, sb, ha, hb)
+                                    : fd11(f, sa, sb, ha, hb);
+}
+static double DUP(int order, const double* f, long s, double h, double vel) {
+  return (order == 6 || order == 8) ? fdupo(fd_table(order), f, s, h, vel) : fdup(f, s, h, vel);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -306,11 +378,11 @@ static void bssn_point(const orc_params* p, const geom* G, const double* y, long
   for (int v = 0; v < NB; v++) {
     const double* f = y + v * G->npts + q;
     u[v] = f[0];
-    for (int a = 0; a < 3; a++) d1[v][a] = fd1(f, st[a], h[a]);
+    for (int a = 0; a < 3; a++) d1[v][a] = D1(p->fd_order, f, st[a], h[a]);
     for (int a = 0; a < 3; a++) {
-      d2[v][a][a] = fd2(f, st[a], h[a]);
+      d2[v][a][a] = D2(p->fd_order, f, st[a], h[a]);
       for (int b = a + 1; b < 3; b++) {
-        d2[v][a][b] = fd11(f, st[a], st[b], h[a], h[b]);
+        d2[v][a][b] = D11(p->fd_order, f, st[a], st[b], h[a], h[b]);
         d2[v][b][a] = d2[v][a][b];
       }
     }
@@ -319,7 +391,7 @@ static void bssn_point(const orc_params* p, const geom* G, const double* y, long
   for (int v = 0; v < NB; v++) {
     const double* f = y + v * G->npts + q;
     adv[v] = 0.0;
-    for (int k = 0; k < 3; k++) adv[v] += beta[k] * fdup(f, st[k], h[k], beta[k]);
+    for (int k = 0; k < 3; k++) adv[v] += beta[k] * DUP(p->fd_order, f, st[k], h[k], beta[k]);
   }
   /* Kreiss-Oliger dissipation of every variable (added to the right-hand
    * sides in phase 3; the frozen shift and B stay frozen) */
@@ -755,12 +827,12 @@ void orc_stencil(const orc_params* p, const double* f, int kind, int a, int b,
         const long q = idx(&G, i, j, k);
         double v;
         if (kind == 1)
-          v = fd1(f + q, st[a], p->h[a]);
+          v = D1(p->fd_order, f + q, st[a], p->h[a]);
         else if (kind == 2)
-          v = (a == b) ? fd2(f + q, st[a], p->h[a])
-                       : fd11(f + q, st[a], st[b], p->h[a], p->h[b]);
+          v = (a == b) ? D2(p->fd_order, f + q, st[a], p->h[a])
+                       : D11(p->fd_order, f + q, st[a], st[b], p->h[a], p->h[b]);
         else if (kind == 3)
-          v = fdup(f + q, st[a], p->h[a], sgn ? sgn[q] : 1.0);
+          v = DUP(p->fd_order, f + q, st[a], p->h[a], sgn ? sgn[q] : 1.0);
         else
           v = delta6(f + q, st[a]);
         out[q] = v;

@@ -38,6 +38,7 @@ typedef struct {
   int gw_axis;         /* gauge wave direction 0,1,2 */
   double ko_sigma;     /* Kreiss-Oliger dissipation strength (0: none) */
   int enforce;         /* 1: det gt = 1 and tr At = 0 after every RK substage */
+  int fd_order;        /* BSSN finite-difference order: 4 (also 0), 6 or 8 */
 } orc_params;
 
 enum { ORC_WAVE = 1, ORC_BSSN = 2, ORC_WAVE5 = 3 };
