@@ -170,6 +170,20 @@ def main(argv=None) -> int:
     kmx = _events_time(lambda: gmx.rhs(st, rhs), reps)
     print(f"[bench] mixed step {elapsed_mx / args.steps * 1e3:.3f} ms", file=sys.stderr, flush=True)
 
+    # 6th- and 8th-order right-hand sides (cached-load kernels), FP64 and mixed
+    khi = {}
+    for order in (6, 8):
+        gho = order // 2 + 1
+        for name, prec in (("fp64", C.FP64), ("mixed", C.MIXED)):
+            go = C.Grid((n, n, n), gho, h, precision=prec, fd_order=order, **kw)
+            so = go.upload(y0)
+            go.fill_ghosts(so)
+            ro = go.new_state()
+            go.rhs(so, ro)
+            khi[f"bssn_rhs_order{order}_{name}"] = _events_time(lambda: go.rhs(so, ro), 10) * 1e3
+            del go, so, ro
+    torch.cuda.synchronize()
+
     # constraints (FP64 in both modes)
     hm_norms = torch.zeros(4, dtype=torch.float64, device="cuda")
     cws = torch.empty(max(C.lib().chemora_constraints_workspace_bytes(g64.handle) // 8, 1),
@@ -325,7 +339,7 @@ def main(argv=None) -> int:
                        "ghost_periodic_24var": kghost * 1e3, "constraints_fp64": kcons * 1e3,
                        "bssn_rk4_step_fp64": krk64 * 1e3, "bssn_rk4_step_mixed": krkmx * 1e3,
                        "wave256_rk4_step_fp64": kw64 * 1e3, "wave256_rk4_step_mixed": kwmx * 1e3,
-                       "copy_1GiB": kcopy * 1e3},
+                       "copy_1GiB": kcopy * 1e3, **khi},
         "derived": {"bssn_rk4_rhs_updates_per_s_fp64": 4 * pts / krk64,
                     "bssn_rk4_rhs_updates_per_s_mixed": 4 * pts / krkmx,
                     "wave256_rk4_point_steps_per_s_fp64": nw ** 3 / kw64,

@@ -106,7 +106,10 @@ typedef struct {
                         that det gt = 1, then remove the trace of At_ij; 0 = off */
   double ko_sigma;   /* BSSN only (else 0): Kreiss-Oliger dissipation strength >= 0,
                         adding sigma/64 sum_d (sixth difference along d) / h_d to the
-                        right-hand side of every evolved variable; 0 = off */
+                        right-hand side of every evolved variable; 0 = off; order 4 only */
+  int32_t fd_order;  /* finite-difference order (Sec. III.B.2: the order is a parameter of
+                        the discretisation): 0 or 4 (default), or 6 or 8 for BSSN, which
+                        needs ghost >= fd_order/2 + 1 and runs the cached-load kernels */
 } chemora_grid_desc;
 
 /* Create a grid object from a description (copied).  Validates every field

@@ -39,7 +39,8 @@ class GridDesc(ctypes.Structure):
                 ("shift", ctypes.c_int32), ("shift_F", ctypes.c_double),
                 ("eta", ctypes.c_double), ("gw_amp", ctypes.c_double),
                 ("gw_wavelength", ctypes.c_double), ("gw_axis", ctypes.c_int32),
-                ("enforce", ctypes.c_int32), ("ko_sigma", ctypes.c_double)]
+                ("enforce", ctypes.c_int32), ("ko_sigma", ctypes.c_double),
+                ("fd_order", ctypes.c_int32)]
 
 
 class Patch(ctypes.Structure):
@@ -122,7 +123,7 @@ class Grid:
     def __init__(self, n, ghost, h, origin=(0.0, 0.0, 0.0), system=WAVE, precision=FP64,
                  boundary=BC_PERIODIC, slicing=SLICING_1PLUSLOG, shift=SHIFT_GAMMADRIVER,
                  shift_F=0.75, eta=2.0, gw_amp=0.1, gw_wavelength=1.0, gw_axis=0,
-                 enforce=0, ko_sigma=0.0):
+                 enforce=0, ko_sigma=0.0, fd_order=0):
         d = GridDesc()
         d.n[:] = [int(v) for v in n]
         d.ghost = int(ghost)
@@ -132,6 +133,7 @@ class Grid:
         d.slicing, d.shift, d.shift_F, d.eta = slicing, shift, float(shift_F), float(eta)
         d.gw_amp, d.gw_wavelength, d.gw_axis = float(gw_amp), float(gw_wavelength), gw_axis
         d.enforce, d.ko_sigma = int(enforce), float(ko_sigma)
+        d.fd_order = int(fd_order)
         self.desc = d
         h_ = ctypes.c_void_p()
         check(lib().chemora_grid_create(ctypes.byref(d), ctypes.byref(h_)))

@@ -104,6 +104,18 @@ int validate_desc(const chemora_grid_desc* d) {
     return fail(CHEMORA_ERR_INVALID, "ko_sigma must be finite and >= 0");
   if (d->system != CHEMORA_BSSN && (d->enforce != 0 || d->ko_sigma != 0.0))
     return fail(CHEMORA_ERR_INVALID, "enforce and ko_sigma apply to the BSSN system only");
+  if (d->fd_order != 0 && d->fd_order != 4 && d->fd_order != 6 && d->fd_order != 8)
+    return fail(CHEMORA_ERR_INVALID, "fd_order must be 0, 4, 6 or 8, got %d", d->fd_order);
+  {
+    const int order = d->fd_order == 0 ? 4 : d->fd_order;
+    if (order != 4 && d->system != CHEMORA_BSSN)
+      return fail(CHEMORA_ERR_INVALID, "fd_order 6 and 8 apply to the BSSN system only");
+    if (d->system == CHEMORA_BSSN && d->ghost < order / 2 + 1)
+      return fail(CHEMORA_ERR_INVALID, "fd_order %d needs ghost >= %d, got %d", order,
+                  order / 2 + 1, d->ghost);
+    if (order != 4 && d->ko_sigma != 0.0)
+      return fail(CHEMORA_ERR_INVALID, "ko_sigma needs fd_order 4");
+  }
   // element strides of a grid function must fit in 32 bits
   const long long e0 = d->n[0] + 2LL * d->ghost, e1 = d->n[1] + 2LL * d->ghost;
   const long long e2 = d->n[2] + 2LL * d->ghost;
@@ -154,6 +166,7 @@ int chemora_grid_create(const chemora_grid_desc* desc, chemora_grid** out) {
   P.gw_axis = desc->gw_axis;
   P.enforce = desc->enforce;
   P.ko_sigma = desc->ko_sigma;
+  P.fd_order = desc->fd_order == 0 ? 4 : desc->fd_order;
   *out = g;
   return CHEMORA_OK;
 }
@@ -295,7 +308,7 @@ int64_t chemora_constraints_workspace_bytes(const chemora_grid* grid) {
     fail(CHEMORA_ERR_INVALID, "grid is NULL");
     return -1;
   }
-  return constraints_partial_count(grid->geo) * (int64_t)sizeof(double);
+  return constraints_partial_count(grid->geo, grid->par.fd_order) * (int64_t)sizeof(double);
 }
 
 int chemora_constraints(chemora_grid* grid, const double* state, double* hm, double* norms,

@@ -504,6 +504,8 @@ int validate_patches(const chemora_patch* patches, int32_t np, int* precision) {
     if (d.system != CHEMORA_BSSN || d.boundary != CHEMORA_BC_GAUGEWAVE)
       return fail(CHEMORA_ERR_INVALID,
                   "patch %d: batches need BSSN grids with the gauge-wave boundary", q);
+    if (d.fd_order != 0 && d.fd_order != 4)
+      return fail(CHEMORA_ERR_UNSUPPORTED, "patch %d: batches run fd_order 4 only", q);
     if (q == 0) *precision = d.precision;
     if (d.precision != *precision)
       return fail(CHEMORA_ERR_INVALID, "patch %d: all patches must share one precision", q);

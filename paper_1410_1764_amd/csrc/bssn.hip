@@ -48,7 +48,7 @@ __device__ __forceinline__ bool plane_tile(const BssnArgs& a, int b, int& bx, in
 #define CHEMORA_BSSN_WAVES 1
 #endif
 
-template <int STAGE, typename T, int KOM>
+template <int STAGE, typename T, int KOM, int ORD>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(CHEMORA_BSSN_WAVES))) bssn_stage_kernel(BssnArgs a) {
   const Geo& G = a.G;
@@ -64,7 +64,7 @@ __attribute__((amdgpu_waves_per_eu(CHEMORA_BSSN_WAVES))) bssn_stage_kernel(BssnA
     const long long p = i + (long long)j * G.sy + (long long)k * G.sz;
     T rhs[V_N];
     GSrc src{a.io.yin + G.off0 + p, G.sv, G.sy, G.sz};
-    bssn_rhs_point<T, KOM>(src, a.W, a.P, rhs);
+    bssn_rhs_point<T, KOM, ORD>(src, a.W, a.P, rhs);
     bssn_store<STAGE, T>(a.io, G, p, i, j, k, rhs, a.images != 0, a.P.enforce != 0);
   }
 }
@@ -190,7 +190,7 @@ void launch_shape_k(const BssnArgs& a, dim3 grid, hipStream_t s) {
   const int nt = a.ltx * a.lty;
   if (variant == 1 && nt != 256) variant = 2;  // the prefetched LDS source needs 256 threads
   if (variant == 0) {
-    hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T, KOM>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T, KOM, 4>), grid, dim3(256), 0, s, a);
   } else if (variant == 2) {
     if (a.ltx == 32 && async_nbuf() == 3) {
       hipLaunchKernelGGL((bssn_async_kernel<STAGE, T, 32, 8, 3, KOM>), grid, dim3(nt), 0, s, a);
@@ -221,6 +221,16 @@ void launch_shape_k(const BssnArgs& a, dim3 grid, hipStream_t s) {
 // keep their register budget
 template <int STAGE, typename T>
 void launch_shape(const BssnArgs& a, dim3 grid, hipStream_t s) {
+  // orders 6 and 8: the cached-load kernel (the staged kernels' halos are
+  // sized for order 4), without dissipation
+  if (a.P.fd_order == 6) {
+    hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T, KO_OFF, 6>), grid, dim3(256), 0, s, a);
+    return;
+  }
+  if (a.P.fd_order == 8) {
+    hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T, KO_OFF, 8>), grid, dim3(256), 0, s, a);
+    return;
+  }
   if (a.P.ko_sigma != 0.0)
     launch_shape_k<STAGE, T, KO_ON>(a, grid, s);
   else
@@ -246,14 +256,14 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
   BssnArgs a;
   a.G = G;
   a.P = P;
-  a.W = make_weights(P.h, P.ko_sigma);
+  a.W = make_weights(P.h, P.ko_sigma, P.fd_order);
   a.io = io;
   a.images = images ? 1 : 0;
   a.ltx = G.n[0] >= 24 ? 32 : 16;
   a.lty = 256 / a.ltx;
   // with dissipation only the default tiles exist (forced tiles are an
   // ablation of the dissipation-free kernels)
-  if (P.ko_sigma != 0.0) {
+  if (P.ko_sigma != 0.0 || P.fd_order != 4) {
   } else if (kernel_variant(precision) != 0 && forced_tile().w) {
     a.ltx = forced_tile().w;
     a.lty = forced_tile().h;
@@ -266,7 +276,8 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
   const long long xy = (long long)a.tiles[0] * a.tiles[1];
   // global kernel: enough workgroups for several rounds per CU, each
   // marching zc planes; LDS kernel: one plane per workgroup
-  const long long want = kernel_variant(precision) == 0 ? 8192 : (long long)1 << 40;
+  const bool cached = kernel_variant(precision) == 0 || P.fd_order != 4;
+  const long long want = cached ? 8192 : (long long)1 << 40;
   int zsplit = (int)std::min<long long>((want + xy - 1) / xy, G.n[2]);
   if (zsplit > G.n[2]) zsplit = G.n[2];
   if (zsplit < 1) zsplit = 1;
@@ -274,7 +285,7 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
   a.tiles[2] = (G.n[2] + a.zc - 1) / a.zc;
   long long blocks = (long long)a.tiles[0] * a.tiles[1] * a.tiles[2];
   a.cols[0] = a.cols[1] = 0;
-  if (kernel_variant(precision) != 0 && column_order()) {
+  if (!cached && column_order()) {
     const ColumnSplit c = column_split(a.tiles, a.ltx, a.lty);
     if (c.cx > 0) {
       a.cols[0] = c.cx;

@@ -67,26 +67,53 @@ __host__ __device__ constexpr int sidx(int i, int j) {
   return (i < j ? i : j) * (5 - (i < j ? i : j)) / 2 + (i < j ? j : i);
 }
 
-// Stencil weights for one block.
+// Stencil weights for one block: the stencils' integer weights are applied
+// in the code, these carry the common denominators (order 4: 12, 12 and
+// 144; order 6: 60, 180, 3600; order 8: 840, 5040, 840^2).
 struct Weights {
-  double i12h[3];   // 1 / (12 h_d)
-  double i12hh[3];  // 1 / (12 h_d^2)
-  double i144[3];   // 1 / (144 h_a h_b) for (x,y), (x,z), (y,z)
-  double ko[3];     // Kreiss-Oliger: sigma / (64 h_d), all 0 when off
+  double w1[3];   // first derivatives (centred and lopsided): 1 / (den1 h_d)
+  double w2[3];   // pure second derivatives: 1 / (den2 h_d^2)
+  double w11[3];  // mixed: 1 / (den1^2 h_a h_b) for (x,y), (x,z), (y,z)
+  double ko[3];   // Kreiss-Oliger: sigma / (64 h_d), all 0 when off
 };
 
-inline Weights make_weights(const double h[3], double ko_sigma = 0.0) {
+inline Weights make_weights(const double h[3], double ko_sigma = 0.0, int order = 4) {
+  const double den1 = order == 8 ? 840.0 : (order == 6 ? 60.0 : 12.0);
+  const double den2 = order == 8 ? 5040.0 : (order == 6 ? 180.0 : 12.0);
   Weights w;
   for (int d = 0; d < 3; ++d) {
-    w.i12h[d] = 1.0 / (12.0 * h[d]);
-    w.i12hh[d] = 1.0 / (12.0 * h[d] * h[d]);
+    w.w1[d] = 1.0 / (den1 * h[d]);
+    w.w2[d] = 1.0 / (den2 * h[d] * h[d]);
     w.ko[d] = ko_sigma / (64.0 * h[d]);
   }
-  w.i144[0] = 1.0 / (144.0 * h[0] * h[1]);
-  w.i144[1] = 1.0 / (144.0 * h[0] * h[2]);
-  w.i144[2] = 1.0 / (144.0 * h[1] * h[2]);
+  w.w11[0] = 1.0 / (den1 * den1 * h[0] * h[1]);
+  w.w11[1] = 1.0 / (den1 * den1 * h[0] * h[2]);
+  w.w11[2] = 1.0 / (den1 * den1 * h[1] * h[2]);
   return w;
 }
+
+// Integer weights of the 6th- and 8th-order operators (order 4 is written
+// out in axis_derivs): centred first derivative A_k on f_k - f_-k and
+// second derivative B_k on (f_k - f0) + (f_-k - f0), k = 1..M; lopsided
+// first derivative U on f_k - f0 at offsets k = -(M-1) .. M+1 towards the
+// upwind side (index k + M - 1; the centre's weight is implied).  Each is
+// the unique stencil on its points exact for polynomials up to the order.
+template <int ORD>
+struct FDC;
+template <>
+struct FDC<6> {
+  static constexpr int M = 3;
+  static constexpr double A[3] = {45.0, -9.0, 1.0};
+  static constexpr double B[3] = {270.0, -27.0, 2.0};
+  static constexpr double U[7] = {2.0, -24.0, -35.0, 80.0, -30.0, 8.0, -1.0};
+};
+template <>
+struct FDC<8> {
+  static constexpr int M = 4;
+  static constexpr double A[4] = {672.0, -168.0, 32.0, -3.0};
+  static constexpr double B[4] = {8064.0, -1008.0, 128.0, -9.0};
+  static constexpr double U[9] = {-5.0, 60.0, -420.0, -378.0, 1050.0, -420.0, 140.0, -30.0, 3.0};
+};
 
 // Stencil accessors.  A grid function's neighbourhood is read through an
 // accessor f(dx, dy, dz) (offsets from the point; compile-time constants
@@ -125,7 +152,7 @@ struct GSrc {
 enum : int { KO_OFF = 0, KO_ON = 1, KO_RUNTIME = 2 };
 
 template <typename T, bool D1, bool D2, bool ADV, int KOM, typename Acc>
-__device__ __forceinline__ void axis_derivs(const Acc& f, const Weights& w, const bool bpos[3],
+__device__ __forceinline__ void axis_derivs4(const Acc& f, const Weights& w, const bool bpos[3],
                                             const T beta[3], T d1[3], T d2[3], T& adv) {
   const double f0 = f(0, 0, 0);
   adv = (T)0;
@@ -134,15 +161,15 @@ __device__ __forceinline__ void axis_derivs(const Acc& f, const Weights& w, cons
     const int ex = d == 0, ey = d == 1, ez = d == 2;
     const double m1 = f(-ex, -ey, -ez), p1 = f(ex, ey, ez);
     const double m2 = f(-2 * ex, -2 * ey, -2 * ez), p2 = f(2 * ex, 2 * ey, 2 * ez);
-    if (D1) d1[d] = ((T)8 * (T)(p1 - m1) - (T)(p2 - m2)) * (T)w.i12h[d];
+    if (D1) d1[d] = ((T)8 * (T)(p1 - m1) - (T)(p2 - m2)) * (T)w.w1[d];
     if (D2)
-      d2[d] = ((T)16 * (T)((p1 - f0) + (m1 - f0)) - (T)((p2 - f0) + (m2 - f0))) * (T)w.i12hh[d];
+      d2[d] = ((T)16 * (T)((p1 - f0) + (m1 - f0)) - (T)((p2 - f0) + (m2 - f0))) * (T)w.w2[d];
     if (ADV) {
       const bool up = bpos[d];
       const double u1 = up ? p1 : m1, um1 = up ? m1 : p1, u2 = up ? p2 : m2;
       const double u3 = f.sel(up, 3 * ex, 3 * ey, 3 * ez);
       T l = ((T)18 * (T)(u1 - f0) - (T)3 * (T)(um1 - f0) - (T)6 * (T)(u2 - f0) + (T)(u3 - f0)) *
-            (T)w.i12h[d];
+            (T)w.w1[d];
       l = up ? l : -l;
       adv += beta[d] * l;
     }
@@ -178,15 +205,90 @@ __device__ __forceinline__ void axis_derivs(const Acc& f, const Weights& w, cons
   }
 }
 
+// The same derivatives at order 6 or 8 (cached-load kernels only; no
+// dissipation at these orders).  Sums run over increasing offsets.
+template <typename T, bool D1, bool D2, bool ADV, int ORD, typename Acc>
+__device__ __forceinline__ void axis_derivs_hi(const Acc& f, const Weights& w,
+                                               const bool bpos[3], const T beta[3], T d1[3],
+                                               T d2[3], T& adv) {
+  using C = FDC<ORD>;
+  const double f0 = f(0, 0, 0);
+  adv = (T)0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int ex = d == 0, ey = d == 1, ez = d == 2;
+    if (D1) {
+      T acc = (T)0;
+#pragma unroll
+      for (int k = 1; k <= C::M; ++k)
+        acc += (T)C::A[k - 1] * (T)(f(k * ex, k * ey, k * ez) - f(-k * ex, -k * ey, -k * ez));
+      d1[d] = acc * (T)w.w1[d];
+    }
+    if (D2) {
+      T acc = (T)0;
+#pragma unroll
+      for (int k = 1; k <= C::M; ++k)
+        acc += (T)C::B[k - 1] *
+               (T)((f(k * ex, k * ey, k * ez) - f0) + (f(-k * ex, -k * ey, -k * ez) - f0));
+      d2[d] = acc * (T)w.w2[d];
+    }
+    if (ADV) {
+      const bool up = bpos[d];
+      T acc = (T)0;
+#pragma unroll
+      for (int k = -(C::M - 1); k <= C::M + 1; ++k)
+        if (k != 0) acc += (T)C::U[k + C::M - 1] * (T)(f.sel(up, k * ex, k * ey, k * ez) - f0);
+      T l = acc * (T)w.w1[d];
+      l = up ? l : -l;
+      adv += beta[d] * l;
+    }
+  }
+  if (CHEMORA_BSSN_FENCE >= 2 || (CHEMORA_BSSN_FENCE == 1 && !D2)) {
+    if (D1) {
+      pin(d1[0]);
+      pin(d1[1]);
+      pin(d1[2]);
+    }
+    if (D2) {
+      pin(d2[0]);
+      pin(d2[1]);
+      pin(d2[2]);
+    }
+    if (ADV) pin(adv);
+    fence_memory();
+  }
+}
+
+// ORD: finite-difference order (4, 6 or 8)
+template <typename T, bool D1, bool D2, bool ADV, int KOM, int ORD = 4, typename Acc>
+__device__ __forceinline__ void axis_derivs(const Acc& f, const Weights& w, const bool bpos[3],
+                                            const T beta[3], T d1[3], T d2[3], T& adv) {
+  if constexpr (ORD == 4)
+    axis_derivs4<T, D1, D2, ADV, KOM>(f, w, bpos, beta, d1, d2, adv);
+  else
+    axis_derivs_hi<T, D1, D2, ADV, ORD>(f, w, bpos, beta, d1, d2, adv);
+}
+
 // Mixed derivative d_a d_b f (a < b): first-derivative stencil along both
 // axes, q_mn = [f(m,n) - f(-m,n)] - [f(m,-n) - f(-m,-n)], weights 8 / -1.
-template <typename T, typename Acc>
+template <typename T, int ORD = 4, typename Acc>
 __device__ __forceinline__ T mixed_deriv(const Acc& f, int a, int b, double wab) {
   // value at alpha e_a + beta e_b
   auto at = [&](int alpha, int beta) {
     return f(alpha * (a == 0) + beta * (b == 0), alpha * (a == 1) + beta * (b == 1),
              alpha * (a == 2) + beta * (b == 2));
   };
+  if constexpr (ORD != 4) {  // sum over (i, j) of A_i A_j q_ij, increasing i then j
+    using C = FDC<ORD>;
+    T acc = (T)0;
+#pragma unroll
+    for (int i = 1; i <= C::M; ++i)
+#pragma unroll
+      for (int j = 1; j <= C::M; ++j)
+        acc += (T)(C::A[i - 1] * C::A[j - 1]) *
+               (T)((at(i, j) - at(-i, j)) - (at(i, -j) - at(-i, -j)));
+    return acc * (T)wab;
+  }
   double q[2][2];
 #pragma unroll
   for (int m = 1; m <= 2; ++m)
@@ -197,15 +299,15 @@ __device__ __forceinline__ T mixed_deriv(const Acc& f, int a, int b, double wab)
 }
 
 // All six second derivatives d_a d_b f in symmetric order.
-template <typename T, typename Acc>
+template <typename T, int ORD = 4, typename Acc>
 __device__ __forceinline__ void second_derivs(const Acc& f, const Weights& w, const T d2pure[3],
                                               T dd[6]) {
   dd[0] = d2pure[0];
   dd[3] = d2pure[1];
   dd[5] = d2pure[2];
-  dd[1] = mixed_deriv<T>(f, 0, 1, w.i144[0]);
-  dd[2] = mixed_deriv<T>(f, 0, 2, w.i144[1]);
-  dd[4] = mixed_deriv<T>(f, 1, 2, w.i144[2]);
+  dd[1] = mixed_deriv<T, ORD>(f, 0, 1, w.w11[0]);
+  dd[2] = mixed_deriv<T, ORD>(f, 0, 2, w.w11[1]);
+  dd[4] = mixed_deriv<T, ORD>(f, 1, 2, w.w11[2]);
   if (CHEMORA_BSSN_FENCE >= 1) {
     pin(dd[0]);
     pin(dd[1]);
@@ -221,7 +323,7 @@ __device__ __forceinline__ void second_derivs(const Acc& f, const Weights& w, co
 // conformal metric gu, Christoffels cdu (Gt^i_jk) and their contraction Gd,
 // d_i chi, and the Ricci tensor R_ij (conformal part + chi part).  With ADV
 // the advection terms of gt_ij, Gamt^i and chi are written to rhs as well.
-template <typename T, bool ADV, int KOM, typename Src>
+template <typename T, bool ADV, int KOM, int ORD, typename Src>
 __device__ __forceinline__ void bssn_geometry(Src& src, const Weights& w, const bool bpos[3],
                                               const T beta[3], T chi, const T gt[6], T gu[6],
                                               T cdu[3][6], T Gd[3], T dchi[3], T R[6],
@@ -251,9 +353,9 @@ __device__ __forceinline__ void bssn_geometry(Src& src, const Weights& w, const 
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const auto f = src.acquire(V_GT + q);
-    axis_derivs<T, true, true, ADV, KOM>(f, w, bpos, beta, dgt[q], dpure, adv);
+    axis_derivs<T, true, true, ADV, KOM, ORD>(f, w, bpos, beta, dgt[q], dpure, adv);
     if (ADV) rhs[V_GT + q] = adv;
-    second_derivs<T>(f, w, dpure, dd);
+    second_derivs<T, ORD>(f, w, dpure, dd);
     R[q] = (T)(-0.5) * (gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
                         (T)2 * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]));
   }
@@ -285,7 +387,7 @@ __device__ __forceinline__ void bssn_geometry(Src& src, const Weights& w, const 
     T dG[3][3];  // dG[k][j] = d_j Gt^k
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      axis_derivs<T, true, false, ADV, KOM>(src.acquire(V_GAM + k), w, bpos, beta, dG[k], dpure, adv);
+      axis_derivs<T, true, false, ADV, KOM, ORD>(src.acquire(V_GAM + k), w, bpos, beta, dG[k], dpure, adv);
       if (ADV) rhs[V_GAM + k] = adv;
     }
 #pragma unroll
@@ -327,9 +429,9 @@ __device__ __forceinline__ void bssn_geometry(Src& src, const Weights& w, const 
   // ---- chi: D_i D_j chi = d_i d_j chi - Gt^k_ij d_k chi; chi part of R_ij
   {
     const auto f = src.acquire(V_CHI);
-    axis_derivs<T, true, true, ADV, KOM>(f, w, bpos, beta, dchi, dpure, adv);
+    axis_derivs<T, true, true, ADV, KOM, ORD>(f, w, bpos, beta, dchi, dpure, adv);
     if (ADV) rhs[V_CHI] = adv;
-    second_derivs<T>(f, w, dpure, dd);
+    second_derivs<T, ORD>(f, w, dpure, dd);
 #pragma unroll
     for (int q = 0; q < 6; ++q)
       dd[q] -= cdu[0][q] * dchi[0] + cdu[1][q] * dchi[1] + cdu[2][q] * dchi[2];
@@ -376,7 +478,7 @@ struct ConsOrder {
 };
 
 // Right-hand side of all 24 variables at one point, reading through src.
-template <typename T, int KOM, typename Src>
+template <typename T, int KOM, int ORD = 4, typename Src>
 __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const BssnPar& P,
                                                T rhs[V_N]) {
   // ---- centre values, upwind sides
@@ -399,7 +501,7 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
   }
 
   T gu[6], cdu[3][6], Gd[3], dchi[3], R[6];
-  bssn_geometry<T, true, KOM>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, rhs);
+  bssn_geometry<T, true, KOM, ORD>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, rhs);
   T dd[6], dpure[3], d1v[3], adv;
 
   // ---- lapse: D_i D_j alpha with the physical Christoffels
@@ -409,9 +511,9 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
   T X[6];
   {
     const auto f = src.acquire(V_ALP);
-    axis_derivs<T, true, true, true, KOM>(f, w, bpos, beta, dalp, dpure, adv);
+    axis_derivs<T, true, true, true, KOM, ORD>(f, w, bpos, beta, dalp, dpure, adv);
     rhs[V_ALP] = adv;
-    second_derivs<T>(f, w, dpure, dd);
+    second_derivs<T, ORD>(f, w, dpure, dd);
     const T i2chi = (T)0.5 / chi;
     T uchi[3];  // gt^kl d_l chi
 #pragma unroll
@@ -495,9 +597,9 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const auto f = src.acquire(V_BETA + k);
-    axis_derivs<T, true, true, true, KOM>(f, w, bpos, beta, dbeta[k], dpure, adv);
+    axis_derivs<T, true, true, true, KOM, ORD>(f, w, bpos, beta, dbeta[k], dpure, adv);
     rhs[V_BETA + k] = adv;
-    second_derivs<T>(f, w, dpure, dd);
+    second_derivs<T, ORD>(f, w, dpure, dd);
     lapb[k] = gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
               (T)2 * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]);
     // gdiv[j] += d_j d_k beta^k (k fixed here)
@@ -536,7 +638,7 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
   // ---- trK (first derivatives + advection), At and B (advection only)
   {
     T dK[3];
-    axis_derivs<T, true, false, true, KOM>(src.acquire(V_TRK), w, bpos, beta, dK, dpure, adv);
+    axis_derivs<T, true, false, true, KOM, ORD>(src.acquire(V_TRK), w, bpos, beta, dK, dpure, adv);
     rhs[V_TRK] = adv + rK;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -546,12 +648,12 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
   }
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    axis_derivs<T, false, false, true, KOM>(src.acquire(V_AT + q), w, bpos, beta, d1v, dpure, adv);
+    axis_derivs<T, false, false, true, KOM, ORD>(src.acquire(V_AT + q), w, bpos, beta, d1v, dpure, adv);
     rhs[V_AT + q] = adv + rA[q];
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    axis_derivs<T, false, false, true, KOM>(src.acquire(V_B + q), w, bpos, beta, d1v, dpure, adv);
+    axis_derivs<T, false, false, true, KOM, ORD>(src.acquire(V_B + q), w, bpos, beta, d1v, dpure, adv);
     rhs[V_B + q] = adv;
   }
 

@@ -28,7 +28,7 @@ struct ConsArgs {
 
 // H and M^i at one point, reading through a neighbourhood source (GSrc or
 // the LDS-staged ASrc with the constraints' acquisition order)
-template <typename Src>
+template <int ORD, typename Src>
 __device__ __forceinline__ void constraints_point(Src& src, const Weights& w, double c[4]) {
   const bool bpos[3] = {true, true, true};
   const double beta[3] = {0.0, 0.0, 0.0};
@@ -40,7 +40,7 @@ __device__ __forceinline__ void constraints_point(Src& src, const Weights& w, do
     At[q] = src.center(V_AT + q);
   }
   double gu[6], cdu[3][6], Gd[3], dchi[3], R[6], unused[V_N];
-  bssn_geometry<double, false, KO_OFF>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, unused);
+  bssn_geometry<double, false, KO_OFF, ORD>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, unused);
   const double Rsc = chi * (gu[0] * R[0] + gu[3] * R[3] + gu[5] * R[5] +
                             2.0 * (gu[1] * R[1] + gu[2] * R[2] + gu[4] * R[4]));
   double Atm[3][3], Atu[6];
@@ -64,10 +64,10 @@ __device__ __forceinline__ void constraints_point(Src& src, const Weights& w, do
   c[0] = Rsc + (2.0 / 3.0) * trK * trK - AtAt;
 
   double dpure[3], adv, dK[3], dAt[6][3];
-  axis_derivs<double, true, false, false, KO_OFF>(src.acquire(V_TRK), w, bpos, beta, dK, dpure, adv);
+  axis_derivs<double, true, false, false, KO_OFF, ORD>(src.acquire(V_TRK), w, bpos, beta, dK, dpure, adv);
 #pragma unroll
   for (int q = 0; q < 6; ++q)
-    axis_derivs<double, true, false, false, KO_OFF>(src.acquire(V_AT + q), w, bpos, beta, dAt[q], dpure,
+    axis_derivs<double, true, false, false, KO_OFF, ORD>(src.acquire(V_AT + q), w, bpos, beta, dAt[q], dpure,
                                             adv);
   // DA[j][ab] = D_j At_ab (conformal covariant derivative)
   double DA[3][6];
@@ -103,6 +103,7 @@ __device__ __forceinline__ void constraints_point(Src& src, const Weights& w, do
   }
 }
 
+template <int ORD>
 __global__ void __launch_bounds__(CT) constraints_kernel(ConsArgs a) {
   __shared__ double red[4][CT];
   const Geo& G = a.G;
@@ -120,7 +121,7 @@ __global__ void __launch_bounds__(CT) constraints_kernel(ConsArgs a) {
       const long long p = i + (long long)j * G.sy + (long long)k * G.sz;
       double c[4];
       GSrc src{a.y + G.off0 + p, G.sv, st[1], st[2]};
-      constraints_point(src, a.W, c);
+      constraints_point<ORD>(src, a.W, c);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         sum[q] += c[q] * c[q];
@@ -175,7 +176,7 @@ __global__ void __launch_bounds__(TX * TY) constraints_async_kernel(ConsArgs a) 
   ASrc<TX, TY, NBUF, ConsOrder> src;
   src.init(G, a.y, bufs, x0, y0, k, tx, ty);
   double c[4];
-  constraints_point(src, a.W, c);
+  constraints_point<4>(src, a.W, c);
   const long long p = i + (long long)j * G.sy + (long long)k * G.sz;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -231,10 +232,10 @@ bool staged() {
   return v;
 }
 
-// returns the number of workgroups
-long long plan(const Geo& G, ConsArgs& a) {
+// returns the number of workgroups (the staged kernel exists for order 4)
+long long plan(const Geo& G, int order, ConsArgs& a) {
   a.cols[0] = a.cols[1] = 0;
-  if (staged()) {
+  if (staged() && order == 4) {
     a.ltx = G.n[0] >= 24 ? 32 : 16;
     a.lty = CT / a.ltx;
     a.tiles[0] = (G.n[0] + a.ltx - 1) / a.ltx;
@@ -264,22 +265,26 @@ long long plan(const Geo& G, ConsArgs& a) {
 
 }  // namespace
 
-long long constraints_partial_count(const Geo& G) {
+long long constraints_partial_count(const Geo& G, int order) {
   ConsArgs a;
-  return 4LL * plan(G, a);
+  return 4LL * plan(G, order, a);
 }
 
 hipError_t launch_bssn_constraints(const Geo& G, const BssnPar& P, const double* y, double* hm,
                                    double* norms, double* partial, hipStream_t s) {
   ConsArgs a;
   a.G = G;
-  a.W = make_weights(P.h);
+  a.W = make_weights(P.h, 0.0, P.fd_order);
   a.y = y;
   a.hm = hm;
   a.partial = partial;
-  const int nb = (int)plan(G, a);
-  if (!staged())
-    hipLaunchKernelGGL(constraints_kernel, dim3(nb), dim3(CT), 0, s, a);
+  const int nb = (int)plan(G, P.fd_order, a);
+  if (P.fd_order == 6)
+    hipLaunchKernelGGL(constraints_kernel<6>, dim3(nb), dim3(CT), 0, s, a);
+  else if (P.fd_order == 8)
+    hipLaunchKernelGGL(constraints_kernel<8>, dim3(nb), dim3(CT), 0, s, a);
+  else if (!staged())
+    hipLaunchKernelGGL(constraints_kernel<4>, dim3(nb), dim3(CT), 0, s, a);
   else if (a.ltx == 32 && cons_nbuf() == 6)
     hipLaunchKernelGGL((constraints_async_kernel<32, 8, 6>), dim3(nb), dim3(CT), 0, s, a);
   else if (a.ltx == 32)

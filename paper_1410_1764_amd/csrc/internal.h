@@ -33,6 +33,7 @@ struct BssnPar {
   int gw_axis;
   int enforce;      // det gt = 1, tr At = 0 after every RK substage
   double ko_sigma;  // Kreiss-Oliger dissipation strength (0: none)
+  int fd_order;     // finite-difference order: 4, 6 or 8
 };
 
 // The four classical RK4 substages fused with the right-hand side.  Stage 0
@@ -143,7 +144,7 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
 hipError_t launch_bssn_constraints(const Geo& G, const BssnPar& P, const double* y,
                                    double* hm, double* norms, double* partial,
                                    hipStream_t s);
-long long constraints_partial_count(const Geo& G);
+long long constraints_partial_count(const Geo& G, int order);
 hipError_t launch_probe_copy(void* dst, const void* src, long long nbytes, hipStream_t s);
 
 }  // namespace chemora

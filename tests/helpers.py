@@ -27,7 +27,8 @@ def pair(n, g, h, system, origin=(0.0, 0.0, 0.0), precision=0, boundary=0, **kw)
                 **{k: v for k, v in kw.items() if k != "gw_d"},
                 **({"gw_wavelength": kw["gw_d"]} if "gw_d" in kw else {}))
     okw = {k: v for k, v in kw.items() if k in ("slicing", "shift", "shift_F", "eta", "gw_amp",
-                                                  "gw_d", "gw_axis", "ko_sigma", "enforce")}
+                                                  "gw_d", "gw_axis", "ko_sigma", "enforce",
+                                                  "fd_order")}
     if "gw_wavelength" in kw:
         okw["gw_d"] = kw["gw_wavelength"]
     return gr, oracle.Block(n, g, h, origin, **okw)

@@ -44,6 +44,11 @@ def _create(**kw):
     (dict(ko_sigma=float("inf")), "ko_sigma"),
     (dict(system=C.WAVE, ghost=2, ko_sigma=0.1), "BSSN system only"),
     (dict(system=C.WAVE, ghost=2, enforce=1), "BSSN system only"),
+    (dict(fd_order=5), "fd_order"),
+    (dict(fd_order=6), "ghost >= 4"),
+    (dict(ghost=4, fd_order=8), "ghost >= 5"),
+    (dict(ghost=4, fd_order=6, ko_sigma=0.1), "fd_order 4"),
+    (dict(system=C.WAVE, ghost=4, fd_order=6), "BSSN system only"),
 ])
 def test_grid_create_rejects(kw, msg):
     with pytest.raises(C.ChemoraError) as e:
