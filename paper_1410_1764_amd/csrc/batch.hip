@@ -52,6 +52,8 @@ long long grid_state_elems(const chemora_grid* g);
 namespace {
 
 constexpr int kThreads = 256;
+// staging buffers of the LDS-staged kinds (three: two workgroups per CU fit)
+constexpr int kBatchBufs = 3;
 constexpr int kGhostChunk = 1024;  // ghost points per ghost item
 constexpr int kMaxPatches = 4096;
 
@@ -238,7 +240,7 @@ __device__ __forceinline__ void staged_tile(const PatchDesc& p, const StageIO& i
   const int x0 = bx * TX, y0 = by * TY;
   const int i = x0 + tx, j = y0 + ty;
   T rhs[V_N];
-  ASrc<TX, TY, 6> src;
+  ASrc<TX, TY, kBatchBufs> src;
   src.init(G, io.yin, bufs, x0, y0, k, tx, ty);
   bssn_rhs_point<T, KOM>(src, p.W, p.P, rhs);
   if (i < G.n[0] && j < G.n[1])
@@ -254,8 +256,8 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
   constexpr int TOT = KindShape<KIND>::TOT;
   // separate arrays, one per staging buffer (see bssn_lds.h); a tiny
   // placeholder each for kind 0
-  __shared__ double L0[TOT], L1[TOT], L2[TOT], L3[TOT], L4[TOT], L5[TOT];
-  double* bufs[6] = {L0, L1, L2, L3, L4, L5};
+  __shared__ double L0[TOT], L1[TOT], L2[TOT];
+  double* bufs[3] = {L0, L1, L2};
   __shared__ long long s_lo, s_hi;  // item range of s_patch (interior or ghost)
   // The current patch's descriptor lives in LDS: under register pressure the
   // compiler re-reads descriptor fields (weights, strides) inside the point
