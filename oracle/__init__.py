@@ -23,6 +23,9 @@ What each routine follows in the paper (arXiv:1410.1764):
     thorn (Sec. II).
   * ``constraints``: Hamiltonian and momentum constraints of the physics
     system (Sec. III.B.1) with RMS norms.
+  * ``prolong`` / ``restrict``: coupling of two refinement levels at ratio 2
+    (Sec. IV, the mesh-refinement driver): degree-5 tensor-product Lagrange
+    interpolation into fine ghost zones; injection back onto the coarse level.
 
 Parity status of each routine (pins in ``tests/test_oracle_*.py``): all are
 pinned to closed forms, convergence orders or invariants, except the 1+log /
@@ -93,6 +96,10 @@ def _load():
     lib.orc_bssn_constraints.argtypes = [P, _DP, _DP, _DP]
     lib.orc_stencil.argtypes = [P, _DP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _DP, _DP]
     lib.orc_bssn_enforce.argtypes = [P, _DP]
+    lib.orc_prolong.argtypes = [P, _DP, P, _DP, ctypes.c_int]
+    lib.orc_prolong.restype = ctypes.c_int
+    lib.orc_restrict.argtypes = [P, _DP, P, _DP, ctypes.c_int]
+    lib.orc_restrict.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -232,3 +239,20 @@ def enforce(b: Block, y: np.ndarray) -> None:
     tr At = 0 with respect to the rescaled metric."""
     assert y.shape[0] == NVAR[BSSN]
     _load().orc_bssn_enforce(ctypes.byref(b._p), _ptr(y))
+
+
+def prolong(coarse: Block, yc: np.ndarray, fine: Block, yf: np.ndarray) -> None:
+    """Fill every ghost point of yf (fine block) from yc (coarse block, valid
+    ghosts) by degree-5 tensor-product Lagrange interpolation, ratio 2."""
+    assert yc.shape[0] == yf.shape[0]
+    if _load().orc_prolong(ctypes.byref(coarse._p), _ptr(yc), ctypes.byref(fine._p), _ptr(yf),
+                           yc.shape[0]):
+        raise ValueError("oracle prolong: levels not in ratio 2, misaligned, or out of reach")
+
+
+def restrict(coarse: Block, yc: np.ndarray, fine: Block, yf: np.ndarray) -> None:
+    """Copy fine interior values into the coarse interior points they coincide with."""
+    assert yc.shape[0] == yf.shape[0]
+    if _load().orc_restrict(ctypes.byref(coarse._p), _ptr(yc), ctypes.byref(fine._p), _ptr(yf),
+                            yc.shape[0]):
+        raise ValueError("oracle restrict: levels not in ratio 2 or misaligned")

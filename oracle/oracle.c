@@ -838,3 +838,118 @@ void orc_stencil(const orc_params* p, const double* f, int kind, int a, int b,
         out[q] = v;
       }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Two refinement levels (Sec. IV: Carpet's mesh refinement couples patches
+ * of different resolution through their ghost zones).  Refinement ratio 2:
+ * h_coarse = 2 h_fine on every axis, and every fine point either coincides
+ * with a coarse point or lies half-way between two.
+ *
+ * Prolongation fills every ghost point of the fine block from the coarse
+ * block (whose ghosts must be valid): per axis, a coincident point takes the
+ * coarse value, a half-way point the degree-5 Lagrange interpolant through
+ * the coarse points at offsets -2 .. 3 around it, weights
+ * (3, -25, 150, 150, -25, 3) / 256; the tensor product over the three axes,
+ * summed z outermost, x innermost.
+ *
+ * Restriction copies fine values into every coarse interior point that
+ * coincides with a fine interior point (injection).
+ *
+ * Both return 1 (and do nothing) if the spacings are not in ratio 2, the
+ * fine points are not aligned with the coarse ones, or (prolongation) a
+ * coarse stencil point lies outside the coarse block's extended range.   */
+
+static int axis_map(const orc_params* c, const orc_params* f, int d, int i, int* base,
+                    int* half) {
+  const double r = (f->origin[d] + i * f->h[d] - c->origin[d]) / c->h[d];
+  const double fl = floor(r + 1e-9);
+  const double fr = r - fl;
+  if (fabs(fr) < 1e-9) {
+    *half = 0;
+  } else if (fabs(fr - 0.5) < 1e-9) {
+    *half = 1;
+  } else {
+    return 1;
+  }
+  *base = (int)fl;
+  return 0;
+}
+
+static int check_levels(const orc_params* c, const orc_params* f) {
+  for (int d = 0; d < 3; d++) {
+    if (fabs(c->h[d] - 2.0 * f->h[d]) > 1e-12 * c->h[d]) return 1;
+    const double off = (f->origin[d] - c->origin[d]) / f->h[d];
+    if (fabs(off - floor(off + 0.5)) > 1e-9) return 1;
+  }
+  return 0;
+}
+
+int orc_prolong(const orc_params* cp, const double* yc, const orc_params* fp, double* yf,
+                int nvar) {
+  if (check_levels(cp, fp)) return 1;
+  const geom C = mkgeom(cp), F = mkgeom(fp);
+  static const double W[6] = {3.0 / 256, -25.0 / 256, 150.0 / 256,
+                              150.0 / 256, -25.0 / 256, 3.0 / 256};
+  /* reach check over the fine extended range */
+  for (int d = 0; d < 3; d++)
+    for (int i = -F.g; i < F.n[d] + F.g; i++) {
+      int b, hf;
+      if (axis_map(cp, fp, d, i, &b, &hf)) return 1;
+      const int lo = hf ? b - 2 : b, hi = hf ? b + 3 : b;
+      if (lo < -C.g || hi >= C.n[d] + C.g) return 1;
+    }
+  int fail = 0;
+#pragma omp parallel for schedule(static) reduction(| : fail)
+  for (int k = -F.g; k < F.n[2] + F.g; k++)
+    for (int j = -F.g; j < F.n[1] + F.g; j++)
+      for (int i = -F.g; i < F.n[0] + F.g; i++) {
+        if (is_interior(&F, i, j, k)) continue;
+        const int ii[3] = {i, j, k};
+        int b[3], hf[3], cnt[3];
+        double w[3][6];
+        for (int d = 0; d < 3; d++) {
+          fail |= axis_map(cp, fp, d, ii[d], &b[d], &hf[d]);
+          if (hf[d]) {
+            cnt[d] = 6;
+            for (int m = 0; m < 6; m++) w[d][m] = W[m];
+            b[d] -= 2;
+          } else {
+            cnt[d] = 1;
+            w[d][0] = 1.0;
+          }
+        }
+        for (int v = 0; v < nvar; v++) {
+          const double* src = yc + (long)v * C.npts;
+          double acc = 0.0;
+          for (int c = 0; c < cnt[2]; c++)
+            for (int bb = 0; bb < cnt[1]; bb++)
+              for (int a = 0; a < cnt[0]; a++)
+                acc += w[2][c] * w[1][bb] * w[0][a] *
+                       src[idx(&C, b[0] + a, b[1] + bb, b[2] + c)];
+          yf[(long)v * F.npts + idx(&F, i, j, k)] = acc;
+        }
+      }
+  return fail;
+}
+
+int orc_restrict(const orc_params* cp, double* yc, const orc_params* fp, const double* yf,
+                 int nvar) {
+  if (check_levels(cp, fp)) return 1;
+  const geom C = mkgeom(cp), F = mkgeom(fp);
+  for (int k = 0; k < C.n[2]; k++)
+    for (int j = 0; j < C.n[1]; j++)
+      for (int i = 0; i < C.n[0]; i++) {
+        const int ii[3] = {i, j, k};
+        int fi[3], inside = 1;
+        for (int d = 0; d < 3; d++) {
+          const double r = (cp->origin[d] + ii[d] * cp->h[d] - fp->origin[d]) / fp->h[d];
+          fi[d] = (int)floor(r + 0.5);
+          if (fabs(r - fi[d]) > 1e-9 || fi[d] < 0 || fi[d] >= F.n[d]) inside = 0;
+        }
+        if (!inside) continue;
+        for (int v = 0; v < nvar; v++)
+          yc[(long)v * C.npts + idx(&C, i, j, k)] =
+              yf[(long)v * F.npts + idx(&F, fi[0], fi[1], fi[2])];
+      }
+  return 0;
+}

@@ -1,0 +1,197 @@
+"""Pins for the oracle's coupling of two refinement levels (Sec. IV: the
+mesh-refinement driver fills a fine patch's ghost zones from the coarser
+level and copies fine results back onto the coarse level).
+
+Pinned to what the mathematics fixes, not to the oracle's weight table:
+  * prolongation reproduces every polynomial of degree <= 5 in each
+    coordinate separately, at every fine ghost point (tensor-product exactness);
+  * on x^6 its error at a half-way point is the Lagrange remainder
+    h_c^6 * prod_m (1/2 - t_m) over the six nodes t_m = -2 .. 3, i.e. exactly
+    -(2.5 * 1.5 * 0.5)^2 h_c^6 (computed from the node positions);
+  * coincident points copy the coarse value bitwise; the fine interior and
+    the coarse state are left alone;
+  * on smooth data the half-way error falls by 2^6 when both levels are
+    refined;
+  * restriction is injection: bitwise copies at coincident points, nothing
+    elsewhere, and restricting a fine grid function sampled from a
+    polynomial gives that polynomial on the coarse grid;
+  * levels that are not in ratio 2, misaligned, or out of reach are refused.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _levels(nc=(20, 18, 16), gc=3, hc=(0.1, 0.08, 0.12), oc=(-0.3, 0.2, -0.1),
+            nf=(16, 14, 12), gf=3, off=(6, 7, 8)):
+    """Coarse block and a fine block inside it: h_f = h_c / 2, fine origin
+    shifted by off fine points (odd offsets start the fine grid half-way)."""
+    c = oracle.Block(nc, gc, hc, oc)
+    hf = tuple(v / 2 for v in hc)
+    of = tuple(oc[d] + off[d] * hf[d] for d in range(3))
+    f = oracle.Block(nf, gf, hf, of)
+    return c, f
+
+
+def _mesh(b):
+    x, y, z = b.coords()
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return X, Y, Z
+
+
+def _ghost_mask(b):
+    m = np.ones(tuple(v + 2 * b.g for v in b.n[::-1]), dtype=bool)
+    g = b.g
+    m[g:g + b.n[2], g:g + b.n[1], g:g + b.n[0]] = False
+    return m
+
+
+def _half_flags(c, f):
+    """Per axis, which fine extended points are half-way between coarse points."""
+    out = []
+    for d in range(3):
+        i = np.arange(-f.g, f.n[d] + f.g)
+        r = (f.origin[d] + i * f.h[d] - c.origin[d]) / c.h[d]
+        out.append(np.abs(r - np.round(r)) > 0.25)
+    return out
+
+
+def test_prolong_polynomials_degree5_per_axis(orc):
+    c, f = _levels()
+    rng = np.random.default_rng(3)
+    cf = rng.standard_normal((6, 6, 6))
+
+    def poly(X, Y, Z):
+        # centre the coordinates so the terms are of similar size
+        X, Y, Z = X - 0.5, Y - 0.9, Z - 0.7
+        return sum(cf[a, b, e] * X ** a * Y ** b * Z ** e
+                   for a in range(6) for b in range(6) for e in range(6))
+
+    yc = poly(*_mesh(c))[None].copy()
+    exact = poly(*_mesh(f))
+    yf = np.full((1,) + exact.shape, np.nan)
+    inner = np.random.default_rng(4).standard_normal(f.interior(yf).shape)
+    yf[(slice(None),) + tuple(slice(f.g, f.g + v) for v in f.n[::-1])] = inner
+    yc_before = yc.copy()
+    oracle.prolong(c, yc, f, yf)
+    gm = _ghost_mask(f)
+    assert np.abs(yf[0][gm] - exact[gm]).max() <= 1e-10 * np.abs(exact).max()
+    assert np.array_equal(f.interior(yf), inner)
+    assert np.array_equal(yc, yc_before)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_prolong_x6_remainder(orc, axis):
+    c, f = _levels()
+    Xc = _mesh(c)[axis]
+    Xf = _mesh(f)[axis]
+    x0 = c.origin[axis]
+    yc = ((Xc - x0) ** 6)[None].copy()
+    yf = f.zeros(1)
+    oracle.prolong(c, yc, f, yf)
+    half = _half_flags(c, f)[axis]
+    gm = _ghost_mask(f)
+    sel = [slice(None)] * 3
+    shape = [1, 1, 1]
+    shape[2 - axis] = -1
+    hm = np.broadcast_to(half.reshape(shape), gm.shape)
+    nodes = np.arange(-2, 4)
+    rem = np.prod(0.5 - nodes)  # Lagrange remainder factor; f^(6)/6! = 1
+    assert rem == -(2.5 * 1.5 * 0.5) ** 2
+    expect_half = (Xf - x0) ** 6 - rem * c.h[axis] ** 6
+    got = yf[0]
+    scale = np.abs((Xf - x0) ** 6).max()
+    m = gm & hm
+    assert m.any() and (gm & ~hm).any()
+    assert np.abs(got[m] - expect_half[m]).max() <= 1e-12 * scale
+    m0 = gm & ~hm
+    assert np.abs(got[m0] - ((Xf - x0) ** 6)[m0]).max() <= 1e-12 * scale
+    del sel
+
+
+def test_prolong_coincident_points_copy_bitwise(orc):
+    c, f = _levels(off=(6, 8, 4))  # even offsets: fine point 0 coincides with a coarse point
+    rng = np.random.default_rng(9)
+    yc = rng.standard_normal((3,) + tuple(v + 2 * c.g for v in c.n[::-1]))
+    yf = f.zeros(3)
+    oracle.prolong(c, yc, f, yf)
+    g = f.g
+    # fine ghost (i, j, k) with all-even offsets from fine point (0,0,0)
+    for (i, j, k) in [(-2, 0, 0), (f.n[0], 2, 4), (-2, -2, -2), (4, f.n[1], 6),
+                      (f.n[0] + 1 - (f.n[0] + 1) % 2, 0, f.n[2])]:
+        ci = tuple((6, 8, 4)[d] // 2 + (i, j, k)[d] // 2 for d in range(3))
+        for v in range(3):
+            assert yf[v, k + g, j + g, i + g] == yc[v, ci[2] + c.g, ci[1] + c.g, ci[0] + c.g]
+
+
+def test_prolong_converges_at_sixth_order(orc):
+    """Smooth non-polynomial data: the worst ghost error falls by about 2^6."""
+    errs = []
+    for s in (1, 2):
+        hc = (0.08 / s, 0.06 / s, 0.1 / s)
+        c, f = _levels(nc=(24 * s, 20 * s, 18 * s), hc=hc, nf=(20 * s, 16 * s, 14 * s),
+                       off=(7 * s - 1 + s % 2, 8 * s - 1 + s % 2, 9 * s - 1 + s % 2))
+
+        def fn(X, Y, Z):
+            return np.sin(2.1 * X + 0.3) * np.cos(1.7 * Y - 0.2) * np.exp(0.8 * Z)
+
+        yc = fn(*_mesh(c))[None].copy()
+        yf = f.zeros(1)
+        oracle.prolong(c, yc, f, yf)
+        gm = _ghost_mask(f)
+        errs.append(np.abs(yf[0][gm] - fn(*_mesh(f))[gm]).max())
+    assert errs[0] / errs[1] > 45.0, errs
+
+
+def test_restrict_injection(orc):
+    c, f = _levels(off=(6, 8, 4))
+    rng = np.random.default_rng(12)
+    yf = rng.standard_normal((2,) + tuple(v + 2 * f.g for v in f.n[::-1]))
+    yc = rng.standard_normal((2,) + tuple(v + 2 * c.g for v in c.n[::-1]))
+    before = yc.copy()
+    oracle.restrict(c, yc, f, yf)
+    changed = np.zeros(yc.shape[1:], dtype=bool)
+    for k in range(c.n[2]):
+        for j in range(c.n[1]):
+            for i in range(c.n[0]):
+                fi = (2 * i - 6, 2 * j - 8, 2 * k - 4)
+                if all(0 <= fi[d] < f.n[d] for d in range(3)):
+                    changed[k + c.g, j + c.g, i + c.g] = True
+                    for v in range(2):
+                        assert yc[v, k + c.g, j + c.g, i + c.g] == \
+                            yf[v, fi[2] + f.g, fi[1] + f.g, fi[0] + f.g]
+    assert changed.sum() == 8 * 7 * 6
+    assert np.array_equal(yc[:, ~changed], before[:, ~changed])
+
+
+def test_restrict_of_sampled_polynomial(orc):
+    c, f = _levels(off=(5, 7, 3))  # odd offsets: coarse points hit odd fine indices
+    poly = lambda X, Y, Z: 1.0 + X - 2 * Y ** 2 + X * Y * Z ** 3
+    yf = poly(*_mesh(f))[None].copy()
+    yc = np.zeros((1,) + tuple(v + 2 * c.g for v in c.n[::-1]))
+    oracle.restrict(c, yc, f, yf)
+    Xc = _mesh(c)
+    e = poly(*Xc)
+    hit = yc[0] != 0.0
+    assert hit.sum() == 8 * 7 * 6
+    assert np.abs(yc[0][hit] - e[hit]).max() <= 1e-13
+
+
+@pytest.mark.parametrize("bad", ["ratio", "misaligned", "reach"])
+def test_levels_refused(orc, bad):
+    if bad == "ratio":
+        c = oracle.Block((20, 18, 16), 3, 0.1)
+        f = oracle.Block((10, 10, 10), 3, 0.1 / 3, (0.5, 0.5, 0.5))
+    elif bad == "misaligned":
+        c = oracle.Block((20, 18, 16), 3, 0.1)
+        f = oracle.Block((10, 10, 10), 3, 0.05, (0.52, 0.5, 0.5))
+    else:  # the fine ghosts need coarse points beyond the coarse ghosts
+        c, f = _levels(off=(-1, 7, 8))
+    yc = np.zeros((1,) + tuple(v + 2 * c.g for v in c.n[::-1]))
+    yf = np.zeros((1,) + tuple(v + 2 * f.g for v in f.n[::-1]))
+    with pytest.raises(ValueError):
+        oracle.prolong(c, yc, f, yf)
+    if bad != "reach":
+        with pytest.raises(ValueError):
+            oracle.restrict(c, yc, f, yf)
