@@ -96,7 +96,8 @@ def _load():
     lib.orc_bssn_constraints.argtypes = [P, _DP, _DP, _DP]
     lib.orc_stencil.argtypes = [P, _DP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _DP, _DP]
     lib.orc_bssn_enforce.argtypes = [P, _DP]
-    lib.orc_prolong.argtypes = [P, _DP, P, _DP, ctypes.c_int]
+    lib.orc_prolong.argtypes = [P, ctypes.POINTER(_DP), _DP, ctypes.c_int, ctypes.c_double, P,
+                                _DP, ctypes.c_int]
     lib.orc_prolong.restype = ctypes.c_int
     lib.orc_restrict.argtypes = [P, _DP, P, _DP, ctypes.c_int]
     lib.orc_restrict.restype = ctypes.c_int
@@ -241,13 +242,21 @@ def enforce(b: Block, y: np.ndarray) -> None:
     _load().orc_bssn_enforce(ctypes.byref(b._p), _ptr(y))
 
 
-def prolong(coarse: Block, yc: np.ndarray, fine: Block, yf: np.ndarray) -> None:
-    """Fill every ghost point of yf (fine block) from yc (coarse block, valid
-    ghosts) by degree-5 tensor-product Lagrange interpolation, ratio 2."""
-    assert yc.shape[0] == yf.shape[0]
-    if _load().orc_prolong(ctypes.byref(coarse._p), _ptr(yc), ctypes.byref(fine._p), _ptr(yf),
-                           yc.shape[0]):
-        raise ValueError("oracle prolong: levels not in ratio 2, misaligned, or out of reach")
+def prolong(coarse: Block, yc, fine: Block, yf: np.ndarray, times=None, t=0.0) -> None:
+    """Fill every ghost point of yf (fine block) from the coarse block (valid
+    ghosts) by degree-5 tensor-product Lagrange interpolation, ratio 2.
+
+    yc is one coarse state, or a list of 1-3 coarse states at ``times``,
+    combined with Lagrange weights in time at ``t``."""
+    levels = [yc] if isinstance(yc, np.ndarray) else list(yc)
+    times = [0.0] * len(levels) if times is None else list(times)
+    assert len(times) == len(levels) and all(a.shape[0] == yf.shape[0] for a in levels)
+    arr = (_DP * len(levels))(*[_ptr(a) for a in levels])
+    tt = np.ascontiguousarray(times, dtype=np.float64)
+    if _load().orc_prolong(ctypes.byref(coarse._p), arr, _ptr(tt), len(levels), float(t),
+                           ctypes.byref(fine._p), _ptr(yf), yf.shape[0]):
+        raise ValueError("oracle prolong: levels not in ratio 2, misaligned, out of reach, "
+                         "or bad time levels")
 
 
 def restrict(coarse: Block, yc: np.ndarray, fine: Block, yf: np.ndarray) -> None:

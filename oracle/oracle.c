@@ -850,7 +850,9 @@ void orc_stencil(const orc_params* p, const double* f, int kind, int a, int b,
  * coarse value, a half-way point the degree-5 Lagrange interpolant through
  * the coarse points at offsets -2 .. 3 around it, weights
  * (3, -25, 150, 150, -25, 3) / 256; the tensor product over the three axes,
- * summed z outermost, x innermost.
+ * summed z outermost, x innermost.  With several coarse time levels y_l at
+ * times t_l the spatial interpolants are combined with the Lagrange weights
+ * in time, prod_{m != l} (t - t_m) / (t_l - t_m), at the requested time t.
  *
  * Restriction copies fine values into every coarse interior point that
  * coincides with a fine interior point (injection).
@@ -884,9 +886,19 @@ static int check_levels(const orc_params* c, const orc_params* f) {
   return 0;
 }
 
-int orc_prolong(const orc_params* cp, const double* yc, const orc_params* fp, double* yf,
-                int nvar) {
+int orc_prolong(const orc_params* cp, const double* const* yc, const double* times, int ntimes,
+                double t, const orc_params* fp, double* yf, int nvar) {
   if (check_levels(cp, fp)) return 1;
+  if (ntimes < 1 || ntimes > 3) return 1;
+  double wt[3];
+  for (int l = 0; l < ntimes; l++) {
+    wt[l] = 1.0;
+    for (int m = 0; m < ntimes; m++)
+      if (m != l) {
+        if (times[l] == times[m]) return 1;
+        wt[l] *= (t - times[m]) / (times[l] - times[m]);
+      }
+  }
   const geom C = mkgeom(cp), F = mkgeom(fp);
   static const double W[6] = {3.0 / 256, -25.0 / 256, 150.0 / 256,
                               150.0 / 256, -25.0 / 256, 3.0 / 256};
@@ -919,14 +931,18 @@ int orc_prolong(const orc_params* cp, const double* yc, const orc_params* fp, do
           }
         }
         for (int v = 0; v < nvar; v++) {
-          const double* src = yc + (long)v * C.npts;
-          double acc = 0.0;
-          for (int c = 0; c < cnt[2]; c++)
-            for (int bb = 0; bb < cnt[1]; bb++)
-              for (int a = 0; a < cnt[0]; a++)
-                acc += w[2][c] * w[1][bb] * w[0][a] *
-                       src[idx(&C, b[0] + a, b[1] + bb, b[2] + c)];
-          yf[(long)v * F.npts + idx(&F, i, j, k)] = acc;
+          double val = 0.0;
+          for (int l = 0; l < ntimes; l++) {
+            const double* src = yc[l] + (long)v * C.npts;
+            double acc = 0.0;
+            for (int c = 0; c < cnt[2]; c++)
+              for (int bb = 0; bb < cnt[1]; bb++)
+                for (int a = 0; a < cnt[0]; a++)
+                  acc += w[2][c] * w[1][bb] * w[0][a] *
+                         src[idx(&C, b[0] + a, b[1] + bb, b[2] + c)];
+            val += wt[l] * acc;
+          }
+          yf[(long)v * F.npts + idx(&F, i, j, k)] = val;
         }
       }
   return fail;

@@ -58,8 +58,8 @@ void orc_bssn_constraints(const orc_params* p, const double* y, double* hm,
 void orc_stencil(const orc_params* p, const double* f, int kind, int a, int b,
                  const double* sgn, double* out);
 void orc_bssn_enforce(const orc_params* p, double* y);
-int  orc_prolong(const orc_params* coarse, const double* yc, const orc_params* fine,
-                 double* yf, int nvar);
+int  orc_prolong(const orc_params* coarse, const double* const* yc, const double* times,
+                 int ntimes, double t, const orc_params* fine, double* yf, int nvar);
 int  orc_restrict(const orc_params* coarse, double* yc, const orc_params* fine,
                   const double* yf, int nvar);
 

@@ -15,6 +15,9 @@ Pinned to what the mathematics fixes, not to the oracle's weight table:
   * restriction is injection: bitwise copies at coincident points, nothing
     elsewhere, and restricting a fine grid function sampled from a
     polynomial gives that polynomial on the coarse grid;
+  * Lagrange interpolation in time reproduces data quadratic in t from three
+    coarse levels and linear data from two, and at a level's own time is
+    bitwise the single-level result;
   * levels that are not in ratio 2, misaligned, or out of reach are refused.
 """
 import numpy as np
@@ -92,7 +95,6 @@ def test_prolong_x6_remainder(orc, axis):
     oracle.prolong(c, yc, f, yf)
     half = _half_flags(c, f)[axis]
     gm = _ghost_mask(f)
-    sel = [slice(None)] * 3
     shape = [1, 1, 1]
     shape[2 - axis] = -1
     hm = np.broadcast_to(half.reshape(shape), gm.shape)
@@ -107,7 +109,6 @@ def test_prolong_x6_remainder(orc, axis):
     assert np.abs(got[m] - expect_half[m]).max() <= 1e-12 * scale
     m0 = gm & ~hm
     assert np.abs(got[m0] - ((Xf - x0) ** 6)[m0]).max() <= 1e-12 * scale
-    del sel
 
 
 def test_prolong_coincident_points_copy_bitwise(orc):
@@ -195,3 +196,41 @@ def test_levels_refused(orc, bad):
     if bad != "reach":
         with pytest.raises(ValueError):
             oracle.restrict(c, yc, f, yf)
+
+
+def test_prolong_in_time(orc):
+    """Lagrange interpolation in time: data quadratic in t is reproduced
+    exactly from three levels, linear data from two; at a level's own time the
+    result is bitwise the single-level prolongation of that level."""
+    c, f = _levels()
+    X, Y, Z = _mesh(c)
+    Xf, Yf, Zf = _mesh(f)
+    sp = lambda X, Y, Z: 1.0 + X * Y - Z ** 3 + 0.5 * X ** 5  # degree <= 5 per axis
+    q = lambda t: 0.7 - 1.3 * t + 2.1 * t * t
+    times = [0.0, 0.05, 0.1]
+    levels = [(sp(X, Y, Z) * q(tl))[None].copy() for tl in times]
+    gm = _ghost_mask(f)
+    for t in (0.025, 0.075, 0.13, -0.02):
+        yf = f.zeros(1)
+        oracle.prolong(c, levels, f, yf, times, t)
+        exact = sp(Xf, Yf, Zf) * q(t)
+        assert np.abs(yf[0][gm] - exact[gm]).max() <= 1e-11 * np.abs(exact).max(), t
+    # two levels: linear in time exact, quadratic not
+    lin = lambda t: 0.4 + 3.0 * t
+    lv2 = [(sp(X, Y, Z) * lin(tl))[None].copy() for tl in times[:2]]
+    yf = f.zeros(1)
+    oracle.prolong(c, lv2, f, yf, times[:2], 0.03)
+    exact = sp(Xf, Yf, Zf) * lin(0.03)
+    assert np.abs(yf[0][gm] - exact[gm]).max() <= 1e-11 * np.abs(exact).max()
+    yf = f.zeros(1)
+    oracle.prolong(c, levels[:2], f, yf, times[:2], 0.03)
+    exact = sp(Xf, Yf, Zf) * q(0.03)
+    assert np.abs(yf[0][gm] - exact[gm]).max() > 1e-6 * np.abs(exact).max()
+    # at a level's own time
+    for l, tl in enumerate(times):
+        a, b = f.zeros(1), f.zeros(1)
+        oracle.prolong(c, levels, f, a, times, tl)
+        oracle.prolong(c, levels[l], f, b)
+        assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        oracle.prolong(c, [levels[0], levels[1]], f, f.zeros(1), [0.1, 0.1], 0.0)
