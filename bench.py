@@ -67,6 +67,56 @@ def _events_time(fn, reps):
     return start.elapsed_time(stop) / 1e3 / reps
 
 
+def _amr_timing(C, torch):
+    """Prolongation (three coarse time levels) and restriction between a 128^3
+    BSSN level and a centred 96^3 fine patch, 24 grid functions; algorithmic
+    bytes: prolongation writes every fine ghost value and reads every coarse
+    value some ghost stencil reaches, once per time level; restriction reads
+    and writes each injected value once."""
+    import numpy as np
+    nc, nf, g, off = 128, 96, 3, 80
+    hc = 1.0 / nc
+    co = C.Grid((nc,) * 3, g, hc, system=C.BSSN, boundary=C.BC_CALLER)
+    fi = C.Grid((nf,) * 3, g, hc / 2, origin=(off * hc / 2,) * 3, system=C.BSSN,
+                boundary=C.BC_CALLER)
+    cs = [co.new_state() for _ in range(3)]
+    for q, s in enumerate(cs):
+        s.fill_(1.0 + q)
+    fs = fi.new_state()
+    fs.zero_()
+    times = [0.0, 0.5, 1.0]
+    C.prolong(co, cs, fi, fs, times, 0.3)
+    kp = _events_time(lambda: C.prolong(co, cs, fi, fs, times, 0.3), 20)
+    C.restrict(co, cs[0], fi, fs)
+    kr = _events_time(lambda: C.restrict(co, cs[0], fi, fs), 20)
+    # coarse points reached: per axis, by ghost coordinates and by all coordinates
+    def reach(idx):
+        out = set()
+        for i in idx:
+            q = off + i
+            b = q // 2
+            out.update(range(b - 2, b + 4) if q & 1 else [b])
+        return sorted(out)
+    rg = np.array(reach(list(range(-g, 0)) + list(range(nf, nf + g)))) + g
+    ra = np.array(reach(range(-g, nf + g))) + g
+    m = np.zeros((nc + 2 * g,) * 3, dtype=bool)
+    m[np.ix_(ra, ra, rg)] = True
+    m[np.ix_(ra, rg, ra)] = True
+    m[np.ix_(rg, ra, ra)] = True
+    ghosts = (nf + 2 * g) ** 3 - nf ** 3
+    pbytes = 24 * 8 * (ghosts + 3 * int(m.sum()))
+    ninj = (nf // 2) ** 3
+    rbytes = 24 * 8 * 2 * ninj
+    del cs, fs
+    torch.cuda.synchronize()
+    return {"workload": f"{nf}^3 fine patch (ghost {g}) in the {nc}^3 BSSN level, 24 grid "
+                        "functions, prolongation from 3 coarse time levels",
+            "prolong_ms": kp * 1e3, "prolong_bytes": pbytes,
+            "prolong_GBps": pbytes / kp / 1e9, "fine_ghost_points": ghosts,
+            "restrict_ms": kr * 1e3, "restrict_bytes": rbytes,
+            "restrict_GBps": rbytes / kr / 1e9}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +301,11 @@ def main(argv=None) -> int:
         batch["patches"] = len(specs)
         print("[bench] batch done", file=sys.stderr, flush=True)
 
+    # two refinement levels: a 96^3 fine patch (ghost 3) centred in the 128^3
+    # BSSN level, prolongation from three coarse time levels and restriction
+    amr = _amr_timing(C, torch)
+    print("[bench] amr done", file=sys.stderr, flush=True)
+
     # streaming copy: achievable bandwidth and the counter calibration kernel
     nbytes = 1 << 30
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -347,6 +402,7 @@ def main(argv=None) -> int:
                     "wave256_rk4_GBps_mixed": 272 * nw ** 3 / kwmx / 1e9,
                     "copy_GBps": copy_bw / 1e9},
         "batch64": batch or None,
+        "amr": amr,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -218,6 +218,40 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
  * chemora_autotune, the tuned one): tile[0..2] in points. */
 int chemora_batch_tile(const int32_t n[3], int32_t precision, int32_t tile[3]);
 
+/* ---- two refinement levels (Sec. IV: the mesh-refinement driver) ------ */
+
+/* Levels pair: a coarse and a fine grid of the same system with
+ * h_coarse = 2 h_fine on every axis and the fine origin a whole number of
+ * fine spacings from the coarse origin (within 1e-9 of one).  Fine point i
+ * then either coincides with a coarse point or lies half-way between two.
+ * Both grids may use either precision: the values moved are FP64. */
+
+/* Prolongation: fill every ghost point of fine_state from the coarse level.
+ * Per axis a coincident point takes the coarse value and a half-way point
+ * the degree-5 Lagrange interpolant through the six coarse points around
+ * it (weights (3, -25, 150, 150, -25, 3)/256); the tensor product over the
+ * axes.  coarse_states: host array of ntimes (1..3) device states of the
+ * coarse grid at the distinct times times[0..ntimes-1] (host array), with
+ * valid ghost zones; they are combined with the Lagrange weights in time at
+ * time t (t outside the levels' span extrapolates).  The fine interior and
+ * the coarse states are not written.  Errors (INVALID): levels not a pair as
+ * above, different systems, a fine ghost point whose coarse stencil would
+ * leave the coarse extended block, a coarse block with fewer than 6
+ * extended points along an axis, bad times, NULL, misaligned or
+ * overlapping states. */
+int chemora_prolong(const chemora_grid* coarse, const double* const* coarse_states,
+                    const double* times, int32_t ntimes, double t, const chemora_grid* fine,
+                    double* fine_state, chemora_stream stream);
+
+/* Restriction by injection: every interior point of coarse_state that
+ * coincides with an interior point of the fine grid takes that point's
+ * value, for every grid function; nothing else is written (the coarse ghost
+ * zones are the caller's to refill).  No coinciding points: nothing to do,
+ * CHEMORA_OK.  Errors (INVALID): levels not a pair, different systems,
+ * NULL, misaligned or overlapping states. */
+int chemora_restrict(const chemora_grid* coarse, double* coarse_state, const chemora_grid* fine,
+                     const double* fine_state, chemora_stream stream);
+
 /* ---- measurement helper --------------------------------------------- */
 
 /* Streaming copy of nbytes (multiple of 16) from src to dst on stream: the

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libchemora.so")
 SOURCES = ["api.cpp", "ghost.hip", "wave.hip", "wave5.hip", "bssn.hip", "constraints.hip", "batch.hip",
-           "probe.hip"]
+           "amr.hip", "probe.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled: hipcc only emits ordinary FP32 ops

@@ -81,6 +81,9 @@ def lib():
         "chemora_autotune": (ctypes.c_int, [ctypes.POINTER(Patch), i32, _vp, ctypes.c_char_p]),
         "chemora_batch_tile": (ctypes.c_int, [ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]),
         "chemora_probe_copy": (ctypes.c_int, [_vp, _vp, i64, _vp]),
+        "chemora_prolong": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(dbl), i32,
+                                           dbl, _vp, _vp, _vp]),
+        "chemora_restrict": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
         "chemora_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -242,6 +245,24 @@ class Grid:
 
 def probe_copy(dst, src, nbytes: int, stream=None):
     check(lib().chemora_probe_copy(_ptr(dst), _ptr(src), int(nbytes), _stream(stream)))
+
+
+def prolong(coarse: "Grid", coarse_states, fine: "Grid", fine_state, times=None, t=0.0,
+            stream=None):
+    """Fill fine_state's ghost zones from one to three coarse states (at
+    ``times``, combined at time ``t``); see chemora_prolong."""
+    levels = [coarse_states] if hasattr(coarse_states, "data_ptr") else list(coarse_states)
+    times = [0.0] * len(levels) if times is None else list(times)
+    ptrs = (_vp * len(levels))(*[s.data_ptr() for s in levels])
+    tt = (ctypes.c_double * len(times))(*[float(v) for v in times])
+    check(lib().chemora_prolong(coarse.handle, ptrs, tt, len(levels), float(t), fine.handle,
+                                _ptr(fine_state), _stream(stream)))
+
+
+def restrict(coarse: "Grid", coarse_state, fine: "Grid", fine_state, stream=None):
+    """Inject fine interior values into the coinciding coarse interior points."""
+    check(lib().chemora_restrict(coarse.handle, _ptr(coarse_state), fine.handle,
+                                 _ptr(fine_state), _stream(stream)))
 
 
 def batch_meta_bytes(npatches: int) -> int:

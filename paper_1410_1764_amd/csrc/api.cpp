@@ -3,6 +3,7 @@
 // code only; every kernel launch goes through the launchers in internal.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -358,6 +359,109 @@ int chemora_probe_copy(void* dst, const void* src, int64_t nbytes, chemora_strea
     return fail(CHEMORA_ERR_INVALID, "dst and src must be 16-byte aligned");
   return device_status(launch_probe_copy(dst, src, nbytes, static_cast<hipStream_t>(stream)),
                        "copy probe launch");
+}
+
+// Two refinement levels: checks the pair and returns the fine origin's
+// offset from the coarse origin in fine spacings.
+static int level_pair(const chemora_grid* c, const chemora_grid* f, int off[3]) {
+  if (!c || !f) return fail(CHEMORA_ERR_INVALID, "coarse and fine grids must not be NULL");
+  if (c->d.system != f->d.system)
+    return fail(CHEMORA_ERR_INVALID, "coarse and fine grids hold different systems");
+  for (int a = 0; a < 3; ++a) {
+    if (std::fabs(c->d.h[a] - 2.0 * f->d.h[a]) > 1e-12 * c->d.h[a])
+      return fail(CHEMORA_ERR_INVALID, "h[%d]: coarse spacing must be twice the fine spacing", a);
+    const double r = (f->d.origin[a] - c->d.origin[a]) / f->d.h[a];
+    const double q = std::floor(r + 0.5);
+    if (std::fabs(r - q) > 1e-9 || std::fabs(q) > 1e9)
+      return fail(CHEMORA_ERR_INVALID,
+                  "origin[%d]: the fine origin is not a whole number of fine spacings from the "
+                  "coarse origin", a);
+    off[a] = (int)q;
+  }
+  return CHEMORA_OK;
+}
+
+static bool overlaps(const void* a, long long an, const void* b, long long bn) {
+  const char *x = static_cast<const char*>(a), *y = static_cast<const char*>(b);
+  return x < y + bn && y < x + an;
+}
+
+int chemora_prolong(const chemora_grid* coarse, const double* const* coarse_states,
+                    const double* times, int32_t ntimes, double t, const chemora_grid* fine,
+                    double* fine_state, chemora_stream stream) {
+  int off[3];
+  int st = level_pair(coarse, fine, off);
+  if (st != CHEMORA_OK) return st;
+  if (ntimes < 1 || ntimes > kMaxTimeLevels)
+    return fail(CHEMORA_ERR_INVALID, "ntimes must be in [1, %d], got %d", kMaxTimeLevels, ntimes);
+  if (!coarse_states || !times || !fine_state)
+    return fail(CHEMORA_ERR_INVALID, "coarse_states, times and fine_state must not be NULL");
+  if (!std::isfinite(t)) return fail(CHEMORA_ERR_INVALID, "t must be finite");
+  if (!aligned(fine_state)) return fail(CHEMORA_ERR_INVALID, "fine_state must be 256-byte aligned");
+  const long long cb = coarse->state_elems * 8, fb = fine->state_elems * 8;
+  for (int l = 0; l < ntimes; ++l) {
+    if (!coarse_states[l] || !aligned(coarse_states[l]))
+      return fail(CHEMORA_ERR_INVALID, "coarse_states[%d] is NULL or not 256-byte aligned", l);
+    if (!std::isfinite(times[l])) return fail(CHEMORA_ERR_INVALID, "times[%d] is not finite", l);
+    if (overlaps(coarse_states[l], cb, fine_state, fb))
+      return fail(CHEMORA_ERR_INVALID, "coarse_states[%d] overlaps fine_state", l);
+    for (int m = 0; m < l; ++m)
+      if (times[m] == times[l]) return fail(CHEMORA_ERR_INVALID, "times must be distinct");
+  }
+  const Geo &C = coarse->geo, &F = fine->geo;
+  for (int a = 0; a < 3; ++a) {
+    if (C.n[a] + 2 * C.g < 6)
+      return fail(CHEMORA_ERR_INVALID, "the coarse block needs >= 6 extended points along axis %d",
+                  a);
+    for (int i = -F.g; i < F.n[a] + F.g; ++i) {
+      const long long q = (long long)off[a] + i;
+      const long long b = q >= 0 ? q / 2 : -((-q + 1) / 2);  // floor(q / 2)
+      const long long lo = (q & 1) ? b - 2 : b, hi = (q & 1) ? b + 3 : b;
+      if (lo < -C.g || hi >= C.n[a] + C.g)
+        return fail(CHEMORA_ERR_INVALID,
+                    "fine ghost point %d on axis %d needs coarse points [%lld, %lld], outside the "
+                    "coarse extended range [%d, %d)", i, a, lo, hi, -C.g, C.n[a] + C.g);
+    }
+  }
+  // Lagrange weights in time at t
+  double wt[kMaxTimeLevels];
+  for (int l = 0; l < ntimes; ++l) {
+    wt[l] = 1.0;
+    for (int m = 0; m < ntimes; ++m)
+      if (m != l) wt[l] *= (t - times[m]) / (times[l] - times[m]);
+  }
+  return device_status(launch_prolong(C, coarse_states, wt, ntimes, F, off, coarse->nvars,
+                                      fine_state, static_cast<hipStream_t>(stream)),
+                       "prolongation launch");
+}
+
+int chemora_restrict(const chemora_grid* coarse, double* coarse_state, const chemora_grid* fine,
+                     const double* fine_state, chemora_stream stream) {
+  int off[3];
+  int st = level_pair(coarse, fine, off);
+  if (st != CHEMORA_OK) return st;
+  if (!coarse_state || !fine_state)
+    return fail(CHEMORA_ERR_INVALID, "coarse_state and fine_state must not be NULL");
+  if (!aligned(coarse_state) || !aligned(fine_state))
+    return fail(CHEMORA_ERR_INVALID, "states must be 256-byte aligned");
+  if (overlaps(coarse_state, coarse->state_elems * 8, fine_state, fine->state_elems * 8))
+    return fail(CHEMORA_ERR_INVALID, "coarse_state and fine_state overlap");
+  // coarse interior i coincides with fine point 2 i - off, which must be interior
+  int lo[3], cnt[3];
+  for (int a = 0; a < 3; ++a) {
+    const long long o = off[a];
+    long long l0 = o >= 0 ? (o + 1) / 2 : -((-o) / 2);  // ceil(off / 2): fine index >= 0
+    long long h0 = fine->geo.n[a] - 1 + o;             // fine index <= n_fine - 1
+    h0 = h0 >= 0 ? h0 / 2 : -((-h0 + 1) / 2);           // floor
+    l0 = std::max(l0, 0LL);
+    h0 = std::min(h0, (long long)coarse->geo.n[a] - 1);
+    lo[a] = (int)l0;
+    cnt[a] = h0 >= l0 ? (int)(h0 - l0 + 1) : 0;
+  }
+  if ((long long)cnt[0] * cnt[1] * cnt[2] == 0) return CHEMORA_OK;
+  return device_status(launch_restrict(coarse->geo, coarse_state, fine->geo, fine_state, off, lo,
+                                       cnt, coarse->nvars, static_cast<hipStream_t>(stream)),
+                       "restriction launch");
 }
 
 }  // extern "C"

@@ -11,6 +11,7 @@ namespace chemora {
 
 constexpr int kAlign = 16;  // interior x = 0 starts on a 16-double (128 B) boundary
 constexpr int kMaxGhost = 8;
+constexpr int kMaxTimeLevels = 3;  // coarse time levels a prolongation may combine
 constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
 
 // Device view of one block's geometry (element strides, x fastest).
@@ -146,5 +147,10 @@ hipError_t launch_bssn_constraints(const Geo& G, const BssnPar& P, const double*
                                    hipStream_t s);
 long long constraints_partial_count(const Geo& G, int order);
 hipError_t launch_probe_copy(void* dst, const void* src, long long nbytes, hipStream_t s);
+hipError_t launch_prolong(const Geo& C, const double* const* yc, const double* wt, int ntimes,
+                          const Geo& F, const int off[3], int nvar, double* yf, hipStream_t s);
+hipError_t launch_restrict(const Geo& C, double* yc, const Geo& F, const double* yf,
+                           const int off[3], const int lo[3], const int cnt[3], int nvar,
+                           hipStream_t s);
 
 }  // namespace chemora

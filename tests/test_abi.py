@@ -162,3 +162,51 @@ def test_energy_unsupported_for_other_systems():
     g5 = C.Grid((8, 8, 8), 2, 0.1, system=C.WAVE5)
     assert g5.nvars == 5
     assert C.lib().chemora_energy(g5.handle, None, None, None, None, None) == C.ERR_INVALID
+
+
+def test_level_pair_validation():
+    L = C.lib()
+    co = C.Grid((16, 16, 16), 3, 0.1, system=C.BSSN, boundary=C.BC_CALLER)
+    fi = C.Grid((12, 12, 12), 3, 0.05, origin=(0.3, 0.3, 0.3), system=C.BSSN,
+                boundary=C.BC_CALLER)
+    cs = (ctypes.c_void_p * 3)(1 << 30, 2 << 30, 3 << 30)
+    tt = (ctypes.c_double * 3)(0.0, 0.1, 0.2)
+    fs = ctypes.c_void_p(8 << 30)
+
+    def pro(c=co, f=fi, states=cs, times=tt, n=1, t=0.0, out=fs):
+        return L.chemora_prolong(c.handle, states, times, n, t, f.handle, out, None)
+
+    assert pro(n=0) == C.ERR_INVALID and "ntimes" in C.last_error()
+    assert pro(n=4) == C.ERR_INVALID
+    assert pro(out=None) == C.ERR_INVALID
+    assert pro(out=ctypes.c_void_p((8 << 30) + 8)) == C.ERR_INVALID
+    assert "aligned" in C.last_error()
+    assert pro(t=float("nan")) == C.ERR_INVALID
+    same = (ctypes.c_double * 3)(0.0, 0.0, 0.2)
+    assert pro(times=same, n=2) == C.ERR_INVALID and "distinct" in C.last_error()
+    over = (ctypes.c_void_p * 1)(8 << 30)
+    assert pro(states=over) == C.ERR_INVALID and "overlap" in C.last_error()
+    ratio = C.Grid((12, 12, 12), 3, 0.04, origin=(0.32, 0.32, 0.32), system=C.BSSN,
+                   boundary=C.BC_CALLER)
+    assert pro(f=ratio) == C.ERR_INVALID and "twice" in C.last_error()
+    shifted = C.Grid((12, 12, 12), 3, 0.05, origin=(0.31, 0.3, 0.3), system=C.BSSN,
+                     boundary=C.BC_CALLER)
+    assert pro(f=shifted) == C.ERR_INVALID and "whole number" in C.last_error()
+    wave = C.Grid((12, 12, 12), 3, 0.05, origin=(0.3, 0.3, 0.3), system=C.WAVE,
+                  boundary=C.BC_CALLER)
+    assert pro(f=wave) == C.ERR_INVALID and "systems" in C.last_error()
+    # the fine ghosts would need coarse points beyond the coarse ghost zones
+    far = C.Grid((12, 12, 12), 3, 0.05, origin=(-0.05, 0.3, 0.3), system=C.BSSN,
+                 boundary=C.BC_CALLER)
+    assert pro(f=far) == C.ERR_INVALID and "outside the coarse extended range" in C.last_error()
+    assert L.chemora_restrict(co.handle, None, fi.handle, fs, None) == C.ERR_INVALID
+    assert L.chemora_restrict(co.handle, ctypes.c_void_p(8 << 30), fi.handle, fs,
+                              None) == C.ERR_INVALID
+    assert "overlap" in C.last_error()
+    assert L.chemora_restrict(co.handle, ctypes.c_void_p(1 << 30), ratio.handle, fs,
+                              None) == C.ERR_INVALID
+    # no coinciding interior points: nothing is enqueued
+    away = C.Grid((4, 4, 4), 3, 0.05, origin=(5.0, 5.0, 5.0), system=C.BSSN,
+                  boundary=C.BC_CALLER)
+    assert L.chemora_restrict(co.handle, ctypes.c_void_p(1 << 30), away.handle, fs,
+                              None) == C.OK

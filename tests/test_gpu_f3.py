@@ -1,0 +1,157 @@
+"""Two refinement levels on the GPU against the oracle: prolongation of every
+fine ghost point (one and three coarse time levels, BSSN and the wave
+system, even and odd origin offsets, a fine block that reaches the edge of the
+coarse ghost zones) to 1e-12 per grid function, the fine interior and the
+coarse states untouched; restriction bitwise; and a 96^3 fine patch of a
+128^3 BSSN level at full size, sampled."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1410_1764_amd import chemora as C
+from tests.helpers import pair, parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _levels(nc, gc, hc, oc, nf, gf, off, system):
+    hf = tuple(v / 2 for v in hc)
+    of = tuple(oc[d] + off[d] * hf[d] for d in range(3))
+    gcoarse, bc = pair(nc, gc, hc, system, origin=oc, boundary=C.BC_CALLER)
+    gfine, bf = pair(nf, gf, hf, system, origin=of, boundary=C.BC_CALLER)
+    return gcoarse, bc, gfine, bf
+
+
+def _ext(b, nvar, rng):
+    return rng.standard_normal((nvar,) + tuple(v + 2 * b.g for v in b.n[::-1]))
+
+
+def _ghost_mask(b):
+    m = np.ones(tuple(v + 2 * b.g for v in b.n[::-1]), dtype=bool)
+    m[b.g:b.g + b.n[2], b.g:b.g + b.n[1], b.g:b.g + b.n[0]] = False
+    return m
+
+
+CASES = [
+    # (nc, gc, hc, oc, nf, gf, off, system)
+    ((40, 36, 30), 3, (0.05, 0.04, 0.06), (-0.3, 0.2, -0.1), (37, 29, 21), 3, (7, 8, 9), C.BSSN),
+    ((24, 20, 18), 3, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0), (20, 16, 12), 3, (4, 6, 2), C.BSSN),
+    # fine ghosts reach the outermost coarse ghost points
+    ((16, 16, 16), 3, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0), (28, 27, 26), 3, (1, 2, 3), C.BSSN),
+    ((33, 17, 25), 2, (0.08, 0.05, 0.07), (0.1, -0.2, 0.3), (41, 19, 27), 2, (5, 3, 12), C.WAVE),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("ntimes", [1, 3])
+def test_prolong_matches_oracle(case, ntimes):
+    nc, gc, hc, oc, nf, gf, off, system = CASES[case]
+    print("prolong case", case, "ntimes", ntimes, flush=True)
+    gco, bc, gfi, bf = _levels(nc, gc, hc, oc, nf, gf, off, system)
+    rng = np.random.default_rng(100 + case)
+    nvar = gco.nvars
+    levels = [_ext(bc, nvar, rng) for _ in range(ntimes)]
+    times = [0.0, 0.1, 0.2][:ntimes]
+    t = 0.137 if ntimes == 3 else 0.0
+    fine0 = _ext(bf, nvar, rng)
+    cs = [gco.upload_full(y) for y in levels]
+    fs = gfi.upload_full(fine0)
+    C.prolong(gco, cs, gfi, fs, times, t)
+    torch.cuda.synchronize()
+    got = gfi.download(fs, ghosts=True)
+    want = fine0.copy()
+    oracle.prolong(bc, levels, bf, want, times, t)
+    gm = _ghost_mask(bf)
+    e = parity(got[:, gm], want[:, gm])
+    print("  worst", e.max(), flush=True)
+    assert e.max() <= 1e-12
+    assert np.array_equal(got[:, ~gm], fine0[:, ~gm])
+    for y, s in zip(levels, cs):
+        assert np.array_equal(gco.download(s, ghosts=True), y)
+
+
+def test_prolong_at_level_time_is_that_level():
+    nc, gc, hc, oc, nf, gf, off, system = CASES[1]
+    gco, bc, gfi, bf = _levels(nc, gc, hc, oc, nf, gf, off, system)
+    rng = np.random.default_rng(7)
+    levels = [_ext(bc, 24, rng) for _ in range(3)]
+    cs = [gco.upload_full(y) for y in levels]
+    a, b = gfi.new_state(), gfi.new_state()
+    a.zero_()
+    b.zero_()
+    C.prolong(gco, cs, gfi, a, [0.0, 0.5, 1.0], 0.5)
+    C.prolong(gco, cs[1], gfi, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("off", [(4, 6, 2), (5, 7, 3), (-3, 2, -4)])
+def test_restrict_matches_oracle_bitwise(off):
+    nc, nf = (24, 20, 18), (20, 16, 22)
+    gco, bc, gfi, bf = _levels(nc, 3, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0), nf, 3, off, C.BSSN)
+    rng = np.random.default_rng(11)
+    yc, yf = _ext(bc, 24, rng), _ext(bf, 24, rng)
+    cs, fs = gco.upload_full(yc), gfi.upload_full(yf)
+    C.restrict(gco, cs, gfi, fs)
+    torch.cuda.synchronize()
+    want = yc.copy()
+    oracle.restrict(bc, want, bf, yf)
+    assert np.array_equal(gco.download(cs, ghosts=True), want)
+    assert np.array_equal(gfi.download(fs, ghosts=True), yf)
+
+
+def test_restrict_without_overlap_is_a_no_op():
+    gco, bc, gfi, bf = _levels((8, 8, 8), 3, (0.1,) * 3, (0.0,) * 3, (6, 6, 6), 3, (40, 0, 0),
+                               C.BSSN)
+    rng = np.random.default_rng(12)
+    yc = _ext(bc, 24, rng)
+    cs, fs = gco.upload_full(yc), gfi.new_state()
+    fs.zero_()
+    C.restrict(gco, cs, gfi, fs)
+    torch.cuda.synchronize()
+    assert np.array_equal(gco.download(cs, ghosts=True), yc)
+
+
+def test_prolong_96_patch_of_128_level_sampled():
+    """Full size: a 96^3 fine patch (ghost 3) centred in a 128^3 BSSN level,
+    three time levels; 4000 sampled fine ghost points against the oracle on
+    a cut-out coarse block that holds every point they reach."""
+    nc, nf, g = (128,) * 3, (96,) * 3, 3
+    hc = (1 / 128,) * 3
+    off = (80, 80, 80)  # fine block covers coarse points 40 .. 87.5
+    gco, _, gfi, _ = _levels(nc, g, hc, (0.0,) * 3, nf, g, off, C.BSSN)
+    rng = np.random.default_rng(13)
+    times = [0.0, 0.01, 0.02]
+    t = 0.013
+    cs = []
+    for _ in range(3):
+        s = gco.new_state()
+        s.copy_(torch.from_numpy(rng.standard_normal(s.numel())))
+        cs.append(s)
+    fs = gfi.new_state()
+    fs.zero_()
+    C.prolong(gco, cs, gfi, fs, times, t)
+    torch.cuda.synchronize()
+    print("96^3 prolongation done", flush=True)
+    # coarse cut-out: coarse points [lo, lo + m) per axis around the fine block
+    lo, m = 34, 62
+    sub = oracle.Block((m,) * 3, 0, hc, tuple(lo * h for h in hc))
+    cut = []
+    for s in cs:
+        full = gco.download(s, ghosts=True)  # (24, 134, 134, 134), index = point + 3
+        cut.append(np.ascontiguousarray(full[:, lo + g:lo + g + m, lo + g:lo + g + m,
+                                             lo + g:lo + g + m]))
+    got = gfi.download(fs, ghosts=True)
+    gm = _ghost_mask(oracle.Block(nf, g, 1.0))
+    idx = np.argwhere(gm)
+    pick = idx[rng.choice(len(idx), 4000, replace=False)]
+    # one oracle call on a fine block that holds every sampled point as a ghost
+    fb = oracle.Block(nf, g, tuple(v / 2 for v in hc), tuple(off[d] * hc[d] / 2 for d in range(3)))
+    want = np.zeros_like(got)
+    oracle.prolong(sub, cut, fb, want, times, t)
+    a = got[:, pick[:, 0], pick[:, 1], pick[:, 2]]
+    b = want[:, pick[:, 0], pick[:, 1], pick[:, 2]]
+    e = parity(a, b)
+    print("  worst", e.max(), flush=True)
+    assert e.max() <= 1e-12
