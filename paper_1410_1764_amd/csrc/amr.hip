@@ -13,14 +13,19 @@
 // points at offsets -2 .. 3 from the lower neighbour (half-way), weights
 // (3, -25, 150, 150, -25, 3) / 256; the tensor product over the axes.  Up to
 // three coarse time levels are combined with Lagrange weights in time that
-// the host computes.  One thread per (ghost point, grid function): the ghost
-// shell is enumerated as the two z slabs, then the two y slabs of the
-// interior planes, then the two x slabs of the interior rows, so that the
-// threads of a wave share their y and z stencils and walk contiguous x.
-// Along x the six taps are always read (a coincident point's weights are
-// one-hot, its six-point window clamped into the coarse block), because
-// neighbouring lanes alternate between coincident and half-way points; the
-// y and z tap counts are uniform along a row.
+// the host computes.
+//
+// The interpolation is separable, so a workgroup takes a tile of fine
+// ghost points in one fine z-plane and works through it axis by axis in
+// LDS: (1) each coarse (x, y) point of the tile's footprint is interpolated
+// in z and combined in time (loads coalesced along x, each coarse value read
+// once per tile and level); (2) those are interpolated in y to the tile's
+// fine rows; (3) in x to its fine points, which are stored.  A point costs
+// about 20 coarse loads instead of the 6 x 6 x 6 per level of a direct
+// evaluation.  The ghost shell is cut into tiles as the two z slabs (64 x 4
+// tiles over whole planes), the two y bands of the interior planes (32 x g)
+// and the two x bands of the interior rows (g x 32); grid.y runs over the
+// grid functions.
 //
 // Restriction (injection): every coarse interior point that coincides with a
 // fine interior point takes that fine value.  One thread per (point, grid
@@ -41,90 +46,124 @@ struct ProlongArgs {
   double wt[kMaxTimeLevels];
   int ntimes;
   double* yf;
-  long long seg_a, seg_b, total;  // ghost counts: z slabs, then + y slabs, then + x slabs
+  int nta, ntb, ntc;  // tiles per slab plane (A), per band row (B), per band column (C)
+  int blocks_a, blocks_b;  // first block of segments B and C
 };
+
+constexpr int kTA_X = 64, kTA_Y = 4;  // z-slab tiles
+constexpr int kTB_X = 32;             // y-band tiles: 32 x g
+constexpr int kTC_Y = 32;             // x-band tiles: g x 32
+constexpr int kFootX = kTA_X / 2 + 7;                      // coarse footprint bounds
+constexpr int kFootY = (kTC_Y > 2 * kMaxGhost ? kTC_Y : 2 * kMaxGhost) / 2 + 7;
+constexpr int kRowsMax = kTC_Y > kMaxGhost ? kTC_Y : kMaxGhost;
 
 __device__ __forceinline__ int floor_half(int q) { return q >> 1; }  // floor(q / 2)
 
-// Fine ghost number p -> fine point (i, j, k).
-__device__ __forceinline__ void ghost_point(const ProlongArgs& a, long long p, int& i, int& j,
-                                            int& k) {
-  const int g = a.F.g, n0 = a.F.n[0], n1 = a.F.n[1], n2 = a.F.n[2];
-  const int ex = n0 + 2 * g, ey = n1 + 2 * g;
-  if (p < a.seg_a) {
-    const long long plane = (long long)ex * ey;
-    const int s = (int)(p / plane);
-    const int r = (int)(p - s * plane);
-    k = s < g ? s - g : n2 + s - g;
-    j = r / ex - g;
-    i = r % ex - g;
-  } else if (p < a.seg_b) {
-    p -= a.seg_a;
-    const long long slab = 2LL * g * ex;
-    k = (int)(p / slab);
-    const int r = (int)(p - k * slab);
-    const int s = r / ex;
-    j = s < g ? s - g : n1 + s - g;
-    i = r % ex - g;
-  } else {
-    p -= a.seg_b;
-    const long long plane = 2LL * g * n1;
-    k = (int)(p / plane);
-    const int r = (int)(p - k * plane);
-    j = r / (2 * g);
-    const int s = r % (2 * g);
-    i = s < g ? s - g : n0 + s - g;
-  }
+// Coarse window [lo, hi] that fine points q0 .. q1 (fine units) reach along
+// an axis, clamped into the coarse extended range [-g, n + g).
+__device__ __forceinline__ void footprint(int q0, int q1, int n, int g, int& lo, int& cnt) {
+  lo = max(floor_half(q0) - 2, -g);
+  const int hi = min(floor_half(q1) + 3, n + g - 1);
+  cnt = hi - lo + 1;
 }
 
 __global__ void __launch_bounds__(256) prolong_kernel(ProlongArgs a) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.total) return;
+  __shared__ double sz_[kFootY * kFootX];   // z- and time-interpolated coarse footprint
+  __shared__ double sy_[kRowsMax * kFootX];  // then y-interpolated to the fine rows
+  const Geo &C = a.C, &F = a.F;
+  const int g = F.g, ex = F.n[0] + 2 * g;
   const int v = blockIdx.y;
-  int i, j, k;
-  ghost_point(a, p, i, j, k);
-  const Geo& C = a.C;
-
-  // x: always six taps, window clamped into the coarse extended range
-  const int qx = a.off[0] + i, bx = floor_half(qx);
-  int x0;
-  double wx[6];
-  if (qx & 1) {
-    x0 = bx - 2;
-    for (int m = 0; m < 6; ++m) wx[m] = kW[m];
-  } else {
-    x0 = min(max(bx - 2, -C.g), C.n[0] + C.g - 6);
-    for (int m = 0; m < 6; ++m) wx[m] = (x0 + m == bx) ? 1.0 : 0.0;
+  int b = blockIdx.x, i0, j0, k, wx, wy;
+  if (b < a.blocks_a) {  // z slabs: whole extended planes
+    const int per = a.nta * ((F.n[1] + 2 * g + kTA_Y - 1) / kTA_Y);
+    const int s = b / per, r = b - s * per;
+    k = s < g ? s - g : F.n[2] + s - g;
+    const int tx = r % a.nta, ty = r / a.nta;
+    i0 = -g + tx * kTA_X;
+    j0 = -g + ty * kTA_Y;
+    wx = min(kTA_X, ex - tx * kTA_X);
+    wy = min(kTA_Y, F.n[1] + 2 * g - ty * kTA_Y);
+  } else if (b < a.blocks_b) {  // y bands of the interior planes
+    b -= a.blocks_a;
+    const int per = 2 * a.ntb;
+    k = b / per;
+    const int r = b - k * per, band = r / a.ntb, tx = r % a.ntb;
+    i0 = -g + tx * kTB_X;
+    j0 = band == 0 ? -g : F.n[1];
+    wx = min(kTB_X, ex - tx * kTB_X);
+    wy = g;
+  } else {  // x bands of the interior rows
+    b -= a.blocks_b;
+    const int per = 2 * a.ntc;
+    k = b / per;
+    const int r = b - k * per, band = r / a.ntc, ty = r % a.ntc;
+    i0 = band == 0 ? -g : F.n[0];
+    j0 = ty * kTC_Y;
+    wx = g;
+    wy = min(kTC_Y, F.n[1] - ty * kTC_Y);
   }
-  // y, z: one tap (coincident) or six (half-way)
-  const int qy = a.off[1] + j, qz = a.off[2] + k;
-  const int ny = (qy & 1) ? 6 : 1, nz = (qz & 1) ? 6 : 1;
-  const int y0 = (qy & 1) ? floor_half(qy) - 2 : floor_half(qy);
-  const int z0 = (qz & 1) ? floor_half(qz) - 2 : floor_half(qz);
+  const int qx0 = a.off[0] + i0, qy0 = a.off[1] + j0, qz = a.off[2] + k;
+  int cx0, fx, cy0, fy;
+  footprint(qx0, qx0 + wx - 1, C.n[0], C.g, cx0, fx);
+  footprint(qy0, qy0 + wy - 1, C.n[1], C.g, cy0, fy);
+  const bool zhalf = qz & 1;
+  const int nz = zhalf ? 6 : 1;
+  const int z0 = zhalf ? floor_half(qz) - 2 : floor_half(qz);
 
-  const long long base = C.off0 + (long long)v * C.sv + x0 + (long long)y0 * C.sy +
-                         (long long)z0 * C.sz;
-  double val = 0.0;
-  for (int l = 0; l < a.ntimes; ++l) {
-    const double* src = a.yc[l] + base;
-    double acc = 0.0;
-    for (int c = 0; c < nz; ++c) {
-      const double wz = nz == 1 ? 1.0 : kW[c];
-      double plane = 0.0;
-      for (int b = 0; b < ny; ++b) {
-        const double wy = ny == 1 ? 1.0 : kW[b];
-        const double* row = src + (long long)c * C.sz + (long long)b * C.sy;
-        double r = 0.0;
+  // (1) z and time
+  const long long cbase = C.off0 + (long long)v * C.sv + (long long)z0 * C.sz;
+  for (int e = threadIdx.x; e < fx * fy; e += blockDim.x) {
+    const int cy = e / fx, cx = e - cy * fx;
+    const long long o = cbase + (cx0 + cx) + (long long)(cy0 + cy) * C.sy;
+    double val = 0.0;
+    for (int l = 0; l < a.ntimes; ++l) {
+      const double* src = a.yc[l] + o;
+      double acc;
+      if (zhalf) {
+        acc = 0.0;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) r += wx[m] * row[m];
-        plane += wy * r;
+        for (int c = 0; c < 6; ++c) acc += kW[c] * src[(long long)c * C.sz];
+      } else {
+        acc = src[0];
       }
-      acc += wz * plane;
+      val += a.wt[l] * acc;
     }
-    val += a.wt[l] * acc;
+    sz_[cy * kFootX + cx] = val;
   }
-  const Geo& F = a.F;
-  a.yf[F.off0 + (long long)v * F.sv + i + (long long)j * F.sy + (long long)k * F.sz] = val;
+  __syncthreads();
+  // (2) y, to the tile's fine rows
+  for (int e = threadIdx.x; e < fx * wy; e += blockDim.x) {
+    const int j = e / fx, cx = e - j * fx;
+    const int qy = qy0 + j;
+    double val;
+    if (qy & 1) {
+      const int r0 = floor_half(qy) - 2 - cy0;
+      val = 0.0;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) val += kW[m] * sz_[(r0 + m) * kFootX + cx];
+    } else {
+      val = sz_[(floor_half(qy) - cy0) * kFootX + cx];
+    }
+    sy_[j * kFootX + cx] = val;
+  }
+  __syncthreads();
+  // (3) x, to the fine points
+  for (int e = threadIdx.x; e < wx * wy; e += blockDim.x) {
+    const int j = e / wx, i = e - j * wx;
+    const int qx = qx0 + i;
+    const double* row = sy_ + j * kFootX;
+    double val;
+    if (qx & 1) {
+      const int c0 = floor_half(qx) - 2 - cx0;
+      val = 0.0;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) val += kW[m] * row[c0 + m];
+    } else {
+      val = row[floor_half(qx) - cx0];
+    }
+    a.yf[F.off0 + (long long)v * F.sv + (i0 + i) + (long long)(j0 + j) * F.sy +
+         (long long)k * F.sz] = val;
+  }
 }
 
 struct RestrictArgs {
@@ -164,11 +203,17 @@ hipError_t launch_prolong(const Geo& C, const double* const* yc, const double* w
   }
   a.ntimes = ntimes;
   a.yf = yf;
-  const long long g = F.g, ex = F.n[0] + 2 * g, ey = F.n[1] + 2 * g;
-  a.seg_a = 2 * g * ex * ey;
-  a.seg_b = a.seg_a + (long long)F.n[2] * 2 * g * ex;
-  a.total = a.seg_b + (long long)F.n[2] * F.n[1] * 2 * g;
-  const dim3 grid((unsigned)((a.total + 255) / 256), (unsigned)nvar);
+  const int g = F.g, ex = F.n[0] + 2 * g, ey = F.n[1] + 2 * g;
+  a.nta = (ex + kTA_X - 1) / kTA_X;
+  a.ntb = (ex + kTB_X - 1) / kTB_X;
+  a.ntc = (F.n[1] + kTC_Y - 1) / kTC_Y;
+  const long long na = 2LL * g * a.nta * ((ey + kTA_Y - 1) / kTA_Y);
+  const long long nb = (long long)F.n[2] * 2 * a.ntb;
+  const long long nc = (long long)F.n[2] * 2 * a.ntc;
+  if (na + nb + nc > 0x7fffffffLL) return hipErrorInvalidValue;
+  a.blocks_a = (int)na;
+  a.blocks_b = (int)(na + nb);
+  const dim3 grid((unsigned)(na + nb + nc), (unsigned)nvar);
   hipLaunchKernelGGL(prolong_kernel, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
