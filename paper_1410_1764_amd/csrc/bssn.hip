@@ -94,6 +94,31 @@ __global__ void __launch_bounds__(TX * TY) bssn_lds_kernel(BssnArgs a) {
                          a.images != 0, a.P.enforce != 0);
 }
 
+// 6th- and 8th-order operators: the tile's radius-(order/2 + 1)
+// neighbourhood of each grid function staged in LDS (HSrc), one plane per
+// workgroup, no dissipation
+template <int STAGE, typename T, int TX, int TY, int ORD>
+__global__ void __launch_bounds__(TX * TY) bssn_hi_kernel(BssnArgs a) {
+  constexpr int R = ORD / 2 + 1;
+  using S = HShape<TX, TY, R>;
+  __shared__ double L0[S::TOTAL], L1[S::TOTAL];
+  __shared__ int tab[S::TOTAL];
+  const Geo& G = a.G;
+  int bx, by, k;
+  if (!plane_tile(a, blockIdx.x, bx, by, k)) return;  // whole workgroup: no barrier yet
+  const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
+  const int x0 = bx * TX, y0 = by * TY;
+  const int i = x0 + tx, j = y0 + ty;
+  const bool active = i < G.n[0] && j < G.n[1];
+  HSrc<TX, TY, R> src;
+  src.init(G, a.io.yin, L0, L1, tab, x0, y0, k, tx, ty);
+  T rhs[V_N];
+  bssn_rhs_point<T, KO_OFF, ORD>(src, a.W, a.P, rhs);
+  if (active)
+    bssn_store<STAGE, T>(a.io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
+                         a.images != 0, a.P.enforce != 0);
+}
+
 template <int STAGE, typename T, int TX, int TY, int NBUF, int KOM>
 __global__ void __launch_bounds__(TX * TY) bssn_async_kernel(BssnArgs a) {
   static_assert(NBUF >= 2 && NBUF <= 6, "1 to 5 grid functions in flight");
@@ -221,14 +246,25 @@ void launch_shape_k(const BssnArgs& a, dim3 grid, hipStream_t s) {
 // keep their register budget
 template <int STAGE, typename T>
 void launch_shape(const BssnArgs& a, dim3 grid, hipStream_t s) {
-  // orders 6 and 8: the cached-load kernel (the staged kernels' halos are
-  // sized for order 4), without dissipation
-  if (a.P.fd_order == 6) {
-    hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T, KO_OFF, 6>), grid, dim3(256), 0, s, a);
-    return;
-  }
-  if (a.P.fd_order == 8) {
-    hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T, KO_OFF, 8>), grid, dim3(256), 0, s, a);
+  // orders 6 and 8, without dissipation: their own staged kernel (wider
+  // halos), or the cached-load kernel (CHEMORA_BSSN_KERNEL=global)
+  if (a.P.fd_order == 6 || a.P.fd_order == 8) {
+    const bool cached = kernel_variant(sizeof(T) == 4 ? CHEMORA_MIXED : CHEMORA_FP64) == 0;
+    if (a.P.fd_order == 6) {
+      if (cached)
+        hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T, KO_OFF, 6>), grid, dim3(256), 0, s, a);
+      else if (a.ltx == 32)
+        hipLaunchKernelGGL((bssn_hi_kernel<STAGE, T, 32, 8, 6>), grid, dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((bssn_hi_kernel<STAGE, T, 16, 16, 6>), grid, dim3(256), 0, s, a);
+    } else {
+      if (cached)
+        hipLaunchKernelGGL((bssn_stage_kernel<STAGE, T, KO_OFF, 8>), grid, dim3(256), 0, s, a);
+      else if (a.ltx == 32)
+        hipLaunchKernelGGL((bssn_hi_kernel<STAGE, T, 32, 8, 8>), grid, dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((bssn_hi_kernel<STAGE, T, 16, 16, 8>), grid, dim3(256), 0, s, a);
+    }
     return;
   }
   if (a.P.ko_sigma != 0.0)
@@ -276,7 +312,7 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
   const long long xy = (long long)a.tiles[0] * a.tiles[1];
   // global kernel: enough workgroups for several rounds per CU, each
   // marching zc planes; LDS kernel: one plane per workgroup
-  const bool cached = kernel_variant(precision) == 0 || P.fd_order != 4;
+  const bool cached = kernel_variant(precision) == 0;
   const long long want = cached ? 8192 : (long long)1 << 40;
   int zsplit = (int)std::min<long long>((want + xy - 1) / xy, G.n[2]);
   if (zsplit > G.n[2]) zsplit = G.n[2];

@@ -141,6 +141,129 @@ struct LSrc {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Staging for the 6th- and 8th-order operators (stencil radius R = order/2 + 1,
+// the reach of the lopsided stencil).  Neighbourhood of a TX x TY tile at
+// plane k: plane k with an R-point halo in x and y (axis and lopsided
+// stencils, xy mixed derivatives); planes k+-1 .. k+-(R-1) with an
+// (R-1)-point halo (xz and yz mixed derivatives, z axis); planes k+-R without
+// halo (z lopsided).  Two buffers, one barrier per grid function: the
+// workgroup loads grid function s into one buffer while no thread can still
+// be reading the grid function two before it.  The element offsets of the
+// staged points are computed once per workgroup into an LDS table, so the
+// per-variable copy is a table lookup, a load and an LDS store per slot.
+template <int TX, int TY, int R>
+struct HShape {
+  static constexpr int NT = TX * TY;
+  static constexpr int W0 = TX + 2 * R, H0 = TY + 2 * R;
+  static constexpr int W1 = TX + 2 * (R - 1), H1 = TY + 2 * (R - 1);
+  static constexpr int N0 = W0 * H0, N1 = W1 * H1, N3 = TX * TY;
+  static constexpr int NMID = 2 * (R - 1);  // planes k+1 .. k+R-1, then k-1 .. k-(R-1)
+  static constexpr int TOTAL = N0 + NMID * N1 + 2 * N3;
+  static constexpr int SLOTS = (TOTAL + NT - 1) / NT;
+  __host__ __device__ static constexpr int seg(int dz) { return dz > 0 ? dz - 1 : R - 2 - dz; }
+};
+
+template <int TX, int TY, int R>
+struct HAcc {
+  using S = HShape<TX, TY, R>;
+  const double* b0;  // plane k at (tx - R, ty - R)
+  const double* b1;  // first middle plane at (tx - R + 1, ty - R + 1)
+  const double* b3;  // plane k+R at (tx, ty); k-R follows at N3
+  __device__ __forceinline__ double operator()(int dx, int dy, int dz) const {
+    if (dz == 0) return b0[(dy + R) * S::W0 + dx + R];
+    if (dz == R) return b3[0];
+    if (dz == -R) return b3[S::N3];
+    return b1[S::seg(dz) * S::N1 + (dy + R - 1) * S::W1 + dx + R - 1];
+  }
+  // +-(dx,dy,dz) along one axis (lopsided stencils)
+  __device__ __forceinline__ double sel(bool up, int dx, int dy, int dz) const {
+    if (dz == 0) {
+      const int c = R * S::W0 + R, o = dy * S::W0 + dx;
+      return b0[up ? c + o : c - o];
+    }
+    if (dz == R || dz == -R) return b3[(up == (dz > 0)) ? 0 : S::N3];
+    const int c = (R - 1) * S::W1 + R - 1;
+    return b1[(up ? S::seg(dz) : S::seg(-dz)) * S::N1 + c];
+  }
+};
+
+template <int TX, int TY, int R>
+struct HSrc {
+  using S = HShape<TX, TY, R>;
+  double* lds0;
+  double* lds1;
+  const int* otab;   // element offset (variable 0) of every staged point
+  const double* Yt;  // yin + off0
+  const double* Yc;  // centre value of variable 0 at the thread's (clamped) point
+  long long sv;
+  int b0o, b1o, b3o;
+  int seq;
+
+  // fills the offset table (all threads) and synchronises
+  __device__ __forceinline__ void init(const Geo& G, const double* yin, double* buf0,
+                                       double* buf1, int* tab, int x0, int y0, int k, int tx,
+                                       int ty) {
+    lds0 = buf0;
+    lds1 = buf1;
+    otab = tab;
+    Yt = yin + G.off0;
+    sv = G.sv;
+    for (int t = ty * TX + tx; t < S::TOTAL; t += S::NT) {
+      int px, py, dz;
+      if (t < S::N0) {
+        dz = 0;
+        py = t / S::W0 - R;
+        px = t % S::W0 - R;
+      } else if (t < S::N0 + S::NMID * S::N1) {
+        const int r = t - S::N0, sgm = r / S::N1, q = r % S::N1;
+        dz = sgm < R - 1 ? sgm + 1 : -(sgm - (R - 1) + 1);
+        py = q / S::W1 - (R - 1);
+        px = q % S::W1 - (R - 1);
+      } else {
+        const int r = t - S::N0 - S::NMID * S::N1, sgm = r / S::N3, q = r % S::N3;
+        dz = sgm == 0 ? R : -R;
+        py = q / TX;
+        px = q % TX;
+      }
+      int gx = x0 + px, gy = y0 + py;
+      gx = gx < -G.g ? -G.g : (gx > G.n[0] + G.g - 1 ? G.n[0] + G.g - 1 : gx);
+      gy = gy < -G.g ? -G.g : (gy > G.n[1] + G.g - 1 ? G.n[1] + G.g - 1 : gy);
+      tab[t] = gx + gy * G.sy + (k + dz) * G.sz;
+    }
+    b0o = ty * S::W0 + tx;
+    b1o = S::N0 + ty * S::W1 + tx;
+    b3o = S::N0 + S::NMID * S::N1 + ty * TX + tx;
+    const int ci = x0 + tx < G.n[0] ? x0 + tx : G.n[0] - 1;
+    const int cj = y0 + ty < G.n[1] ? y0 + ty : G.n[1] - 1;
+    Yc = Yt + ci + (long long)cj * G.sy + (long long)k * G.sz;
+    seq = 0;
+    __syncthreads();
+  }
+
+  __device__ __forceinline__ double center(int v) const { return Yc[v * sv]; }
+
+  __device__ __forceinline__ HAcc<TX, TY, R> acquire(int v) {
+    double* buf = (seq & 1) ? lds1 : lds0;
+    const double* base = Yt + (long long)v * sv;
+    const int tid = (int)threadIdx.x;
+    double r[S::SLOTS];
+#pragma unroll
+    for (int m = 0; m < S::SLOTS; ++m) {
+      const int t = tid + m * S::NT;
+      r[m] = (m < S::SLOTS - 1 || t < S::TOTAL) ? base[otab[t]] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < S::SLOTS; ++m) {
+      const int t = tid + m * S::NT;
+      if (m < S::SLOTS - 1 || t < S::TOTAL) buf[t] = r[m];
+    }
+    __syncthreads();
+    ++seq;
+    return HAcc<TX, TY, R>{buf + b0o, buf + b1o, buf + b3o};
+  }
+};
+
 }  // namespace chemora
 
 namespace chemora {

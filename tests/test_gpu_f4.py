@@ -18,10 +18,13 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("order", [6, 8])
 @pytest.mark.parametrize("gauge", [dict(slicing=0, shift=1), dict(slicing=1, shift=0)])
 @pytest.mark.parametrize("precision,tol", [(C.FP64, 1e-12), (C.MIXED, 1e-5)])
-def test_rhs_high_order(order, gauge, precision, tol):
-    n = (37, 22, 19)
+@pytest.mark.parametrize("n,extra", [((37, 22, 19), 0), ((20, 18, 11), 1)])
+def test_rhs_high_order(order, gauge, precision, tol, n, extra):
+    """32 x 8 tiles (n_x >= 24) and 16 x 16 tiles, both ragged; the second
+    shape with one ghost more than the order needs"""
     h = tuple(1.0 / v for v in n)
-    gr, b = pair(n, order // 2 + 1, h, C.BSSN, precision=precision, fd_order=order, **gauge)
+    gr, b = pair(n, order // 2 + 1 + extra, h, C.BSSN, precision=precision, fd_order=order,
+                 **gauge)
     y0 = _smooth_random(n, 31)
     st = gr.upload(y0)
     gr.fill_ghosts(st)
@@ -30,7 +33,8 @@ def test_rhs_high_order(order, gauge, precision, tol):
     yo = b.embed(y0)
     oracle.fill_periodic(b, yo)
     e = parity(gr.download(r), b.interior(oracle.bssn_rhs(b, yo)))
-    print("rhs order", order, gauge, precision, e.max(), I.BSSN_NAMES[int(np.argmax(e))])
+    print("rhs order", order, n, gauge, precision, e.max(), I.BSSN_NAMES[int(np.argmax(e))],
+          flush=True)
     assert e.max() <= tol
 
 
