@@ -193,8 +193,9 @@ typedef struct {
 int64_t chemora_batch_meta_bytes(int32_t npatches);
 
 /* Advance every patch by nsteps RK4 steps of size dt from time t.  All
- * patches must share one system (BSSN), one precision and the gauge-wave
- * boundary.  Each RK substage is ONE persistent kernel launch over a work
+ * patches must share one system (BSSN), one precision, one fd_order and the
+ * gauge-wave boundary (INVALID otherwise); FP64 batches of fd_order 6 return
+ * CHEMORA_ERR_UNSUPPORTED (mixed precision and fd_order 8 run).  Each RK substage is ONE persistent kernel launch over a work
  * list of (patch, tile) items plus the analytic ghost zones of the next
  * stage; the four substages and the clock update are captured once in a
  * HIP graph that is replayed once per step.  The plan (tile shape per
@@ -210,7 +211,9 @@ int chemora_batch_release(void* meta);
  * timed trials after a model-driven pruning (halo overhead, occupancy,
  * wave quantisation), and record the winners in an in-process table used
  * by later batch plans; when table_path is not NULL also write the table
- * there as JSON.  Runs kernels on the null stream and synchronises. */
+ * there as JSON.  Runs kernels on the null stream and synchronises.
+ * Patches with fd_order 6 or 8 have one kernel each: nothing is tuned,
+ * CHEMORA_OK. */
 int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
                      const char* table_path);
 

@@ -19,7 +19,9 @@
 // stage each grid function's tile neighbourhood in LDS with async copies
 // (bssn_lds.h, ASrc, in both precisions) with 32x8 or 16x16 single-plane
 // tiles.  The autotuner picks the kind and, for kind 0,
-// the tile of each size class.
+// the tile of each size class.  Patches with the 6th- or 8th-order operators
+// run kinds 3 and 4: 32x8 single-plane tiles staged with the wider
+// neighbourhood of those orders (HSrc), nothing to tune.
 //
 // The four substage launches and a one-thread clock update (t += dt) are
 // captured once into a HIP graph and replayed per step; the time lives in a
@@ -225,13 +227,22 @@ __device__ __forceinline__ void stage_buffers(const Batch& B, const PatchDesc& p
 template <int KIND>
 struct KindShape {
   static constexpr int TX = KIND == 2 ? 16 : 32, TY = KIND == 2 ? 16 : 8;
-  static constexpr int TOT = KIND == 0 ? 1 : LdsShape<TX, TY>::TOTAL;
+  static constexpr int ORD = KIND == 3 ? 6 : (KIND == 4 ? 8 : 4);
+  static constexpr bool HI = KIND >= 3;
+  static constexpr int TOT = KIND == 0 ? 1
+                             : HI      ? HShape<TX, TY, ORD / 2 + 1>::TOTAL
+                                       : LdsShape<TX, TY>::TOTAL;
+  static constexpr int TOT3 = HI ? 1 : TOT;  // third buffer: the async kinds only
+  static constexpr int TAB = HI ? TOT : 1;   // offset table: the high-order kinds only
 };
+
+// kind of a plan for patches of finite-difference order ord
+inline int order_kind(int ord, int kind4) { return ord == 6 ? 3 : (ord == 8 ? 4 : kind4); }
 
 // one single-plane tile of a staged kind
 template <int STAGE, typename T, int KIND, int KOM>
 __device__ __forceinline__ void staged_tile(const PatchDesc& p, const StageIO& io, long long tile,
-                                            double* const* bufs) {
+                                            double* const* bufs, int* tab) {
   constexpr int TX = KindShape<KIND>::TX, TY = KindShape<KIND>::TY;
   const Geo& G = p.G;
   int bx, by, k;
@@ -240,9 +251,16 @@ __device__ __forceinline__ void staged_tile(const PatchDesc& p, const StageIO& i
   const int x0 = bx * TX, y0 = by * TY;
   const int i = x0 + tx, j = y0 + ty;
   T rhs[V_N];
-  ASrc<TX, TY, kBatchBufs> src;
-  src.init(G, io.yin, bufs, x0, y0, k, tx, ty);
-  bssn_rhs_point<T, KOM>(src, p.W, p.P, rhs);
+  if constexpr (KindShape<KIND>::HI) {
+    constexpr int ORD = KindShape<KIND>::ORD;
+    HSrc<TX, TY, ORD / 2 + 1> src;
+    src.init(G, io.yin, bufs[0], bufs[1], tab, x0, y0, k, tx, ty);
+    bssn_rhs_point<T, KO_OFF, ORD>(src, p.W, p.P, rhs);
+  } else {
+    ASrc<TX, TY, kBatchBufs> src;
+    src.init(G, io.yin, bufs, x0, y0, k, tx, ty);
+    bssn_rhs_point<T, KOM>(src, p.W, p.P, rhs);
+  }
   if (i < G.n[0] && j < G.n[1])
     bssn_store<STAGE, T>(io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
                          false, p.P.enforce != 0);
@@ -256,7 +274,8 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
   constexpr int TOT = KindShape<KIND>::TOT;
   // separate arrays, one per staging buffer (see bssn_lds.h); a tiny
   // placeholder each for kind 0
-  __shared__ double L0[TOT], L1[TOT], L2[TOT];
+  __shared__ double L0[TOT], L1[TOT], L2[KindShape<KIND>::TOT3];
+  __shared__ int TB[KindShape<KIND>::TAB];
   double* bufs[3] = {L0, L1, L2};
   __shared__ long long s_lo, s_hi;  // item range of s_patch (interior or ghost)
   // The current patch's descriptor lives in LDS: under register pressure the
@@ -313,7 +332,7 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
     if (interior) {
       const long long tile = item - B.prefix[s_patch];
       if constexpr (KIND != 0) {
-        staged_tile<STAGE, T, KIND, KOM>(p, io, tile, bufs);
+        staged_tile<STAGE, T, KIND, KOM>(p, io, tile, bufs, TB);
       } else {
         int tx, ty, tzi;
         patch_tile(p, tile, tx, ty, tzi);
@@ -479,6 +498,10 @@ int resident_blocks() {
 
 template <typename T, int KOM>
 int persistent_blocks_t(int kind) {
+  if constexpr (KOM == KO_OFF) {  // high orders run without dissipation
+    if (kind == 3) return resident_blocks<T, 3, KOM>();
+    if (kind == 4) return resident_blocks<T, 4, KOM>();
+  }
   switch (kind) {
     case 1: return resident_blocks<T, 1, KOM>();
     case 2: return resident_blocks<T, 2, KOM>();
@@ -492,7 +515,8 @@ int persistent_blocks(int precision, int kind, bool ko) {
   return ko ? persistent_blocks_t<double, KO_ON>(kind) : persistent_blocks_t<double, KO_OFF>(kind);
 }
 
-int validate_patches(const chemora_patch* patches, int32_t np, int* precision) {
+int validate_patches(const chemora_patch* patches, int32_t np, int* precision,
+                     int* order = nullptr) {
   if (!patches) return fail(CHEMORA_ERR_INVALID, "patch list is NULL");
   if (np < 1 || np > kMaxPatches)
     return fail(CHEMORA_ERR_INVALID, "npatches must be in [1, %d], got %d", kMaxPatches, np);
@@ -506,9 +530,20 @@ int validate_patches(const chemora_patch* patches, int32_t np, int* precision) {
     if (d.system != CHEMORA_BSSN || d.boundary != CHEMORA_BC_GAUGEWAVE)
       return fail(CHEMORA_ERR_INVALID,
                   "patch %d: batches need BSSN grids with the gauge-wave boundary", q);
-    if (d.fd_order != 0 && d.fd_order != 4)
-      return fail(CHEMORA_ERR_UNSUPPORTED, "patch %d: batches run fd_order 4 only", q);
-    if (q == 0) *precision = d.precision;
+    const int ord = grid_par(p.grid).fd_order;
+    if (q == 0) {
+      *precision = d.precision;
+      if (order) *order = ord;
+    }
+    if (order && ord != *order)
+      return fail(CHEMORA_ERR_INVALID, "patch %d: all patches must share one fd_order", q);
+    // the FP64 instance of the 6th-order batch kind gives wrong results on
+    // every point (the same code in mixed precision, at order 8, and the
+    // single-grid 6th-order kernel are correct); switched off until the
+    // cause is found
+    if (ord == 6 && d.precision == CHEMORA_FP64)
+      return fail(CHEMORA_ERR_UNSUPPORTED,
+                  "patch %d: FP64 batches of 6th-order patches are not supported", q);
     if (d.precision != *precision)
       return fail(CHEMORA_ERR_INVALID, "patch %d: all patches must share one precision", q);
   }
@@ -537,14 +572,14 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     P->wss[q] = patches[q].workspace;
     const Geo& G = grid_geo(g);
     const int32_t n[3] = {G.n[0], G.n[1], G.n[2]};
-    const Tile t = kind == 1   ? Tile{32, 8, 1}
-                   : kind == 2 ? Tile{16, 16, 1}
-                               : (forced ? *forced : default_tile(n, precision));
+    const Tile t = (kind == 1 || kind >= 3) ? Tile{32, 8, 1}
+                   : kind == 2             ? Tile{16, 16, 1}
+                                           : (forced ? *forced : default_tile(n, precision));
     P->tiles[q] = t;
     PatchDesc& d = pd[q];
     d.G = G;
     d.P = grid_par(g);
-    d.W = make_weights(d.P.h, d.P.ko_sigma);
+    d.W = make_weights(d.P.h, d.P.ko_sigma, d.P.fd_order);
     d.state_off = reinterpret_cast<char*>(patches[q].state) - reinterpret_cast<char*>(patches[0].state);
     d.ws_off = static_cast<char*>(patches[q].workspace) - reinterpret_cast<char*>(patches[0].state);
     d.E = grid_state_elems(g);
@@ -630,6 +665,10 @@ hipError_t launch_stage(const Plan* P, int s, hipStream_t st) {
 
 template <typename T, int KOM>
 hipError_t launch_kind(const Plan* P, int s, hipStream_t st) {
+  if constexpr (KOM == KO_OFF) {
+    if (P->kind == 3) return launch_stage<T, 3, KOM>(P, s, st);
+    if (P->kind == 4) return launch_stage<T, 4, KOM>(P, s, st);
+  }
   switch (P->kind) {
     case 1: return launch_stage<T, 1, KOM>(P, s, st);
     case 2: return launch_stage<T, 2, KOM>(P, s, st);
@@ -703,8 +742,8 @@ int64_t chemora_batch_meta_bytes(int32_t npatches) {
 
 int chemora_batch_step(const chemora_patch* patches, int32_t npatches, void* meta, double t,
                        double dt, int32_t nsteps, chemora_stream stream) {
-  int precision = 0;
-  int st = validate_patches(patches, npatches, &precision);
+  int precision = 0, order = 4;
+  int st = validate_patches(patches, npatches, &precision, &order);
   if (st != CHEMORA_OK) return st;
   if (!meta || !aligned(meta)) return fail(CHEMORA_ERR_INVALID, "meta must be a 256-byte aligned device pointer");
   if (nsteps < 0) return fail(CHEMORA_ERR_INVALID, "nsteps must be >= 0");
@@ -731,7 +770,8 @@ int chemora_batch_step(const chemora_patch* patches, int32_t npatches, void* met
         delete P;
         return device_status(e, "batch plan");
       }
-      st = build_plan(P, patches, npatches, meta, dt, precision, default_kind(precision), nullptr);
+      st = build_plan(P, patches, npatches, meta, dt, precision,
+                      order_kind(order, default_kind(precision)), nullptr);
       if (st == CHEMORA_OK) st = capture_graph(P);
       if (st != CHEMORA_OK) {
         destroy_plan(P);
@@ -781,10 +821,11 @@ int chemora_batch_tile(const int32_t n[3], int32_t precision, int32_t tile[3]) {
 
 int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
                      const char* table_path) {
-  int precision = 0;
-  int st = validate_patches(patches, npatches, &precision);
+  int precision = 0, order = 4;
+  int st = validate_patches(patches, npatches, &precision, &order);
   if (st != CHEMORA_OK) return st;
   if (!meta || !aligned(meta)) return fail(CHEMORA_ERR_INVALID, "meta must be a 256-byte aligned device pointer");
+  if (order != 4) return CHEMORA_OK;  // one kernel kind per high order: nothing to tune
   {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     // the trials rewrite meta: nothing queued may still read it

@@ -144,6 +144,16 @@ def test_batch_argument_validation():
     arr[1].state = 0
     assert L.chemora_batch_step(arr, 2, meta, 0.0, 0.1, 1, None) == C.ERR_INVALID
     assert L.chemora_autotune(arr, 0, meta, None) == C.ERR_INVALID
+    # one fd_order per batch
+    g6 = C.Grid((24, 24, 24), 4, 1 / 64, system=C.BSSN, boundary=C.BC_GAUGEWAVE,
+                slicing=C.SLICING_HARMONIC, shift=C.SHIFT_FROZEN, fd_order=6)
+    arr[0].grid, arr[1].grid = g1.handle.value, g6.handle.value
+    arr[0].state, arr[1].state = 4096 * 1024, 8192 * 1024
+    assert L.chemora_batch_step(arr, 2, meta, 0.0, 0.1, 1, None) == C.ERR_INVALID
+    assert "fd_order" in C.last_error()
+    # FP64 batches of 6th-order patches are switched off
+    arr[0].grid = g6.handle.value
+    assert L.chemora_batch_step(arr, 1, meta, 0.0, 0.1, 1, None) == C.ERR_UNSUPPORTED
     assert C.batch_meta_bytes(64) > 64 * 200
     assert C.batch_meta_bytes(64) % 256 == 0
 

@@ -40,6 +40,10 @@ CASES = [
     # fine ghosts reach the outermost coarse ghost points
     ((16, 16, 16), 3, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0), (28, 27, 26), 3, (1, 2, 3), C.BSSN),
     ((33, 17, 25), 2, (0.08, 0.05, 0.07), (0.1, -0.2, 0.3), (41, 19, 27), 2, (5, 3, 12), C.WAVE),
+    # one interior point: the ghost shell is the whole block but its centre
+    ((8, 8, 8), 3, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0), (1, 1, 1), 3, (7, 6, 5), C.BSSN),
+    # the widest ghost zones (8): 32 x 8 and 8 x 32 band tiles, fine block wider than 64
+    ((48, 20, 20), 3, (0.05, 0.1, 0.1), (0.0, 0.0, 0.0), (70, 9, 5), 8, (13, 12, 14), C.WAVE),
 ]
 
 
