@@ -95,14 +95,15 @@ __global__ void __launch_bounds__(TX * TY) bssn_lds_kernel(BssnArgs a) {
 }
 
 // 6th- and 8th-order operators: the tile's radius-(order/2 + 1)
-// neighbourhood of each grid function staged in LDS (HSrc), one plane per
+// neighbourhood of each grid function staged in LDS with asynchronous
+// copies (AHSrc, three buffers: two grid functions in flight), one plane per
 // workgroup, no dissipation
 template <int STAGE, typename T, int TX, int TY, int ORD>
 __global__ void __launch_bounds__(TX * TY) bssn_hi_kernel(BssnArgs a) {
   constexpr int R = ORD / 2 + 1;
   using S = HShape<TX, TY, R>;
-  __shared__ double L0[S::TOTAL], L1[S::TOTAL];
-  __shared__ int tab[S::TOTAL];
+  __shared__ double L0[S::TOTAL], L1[S::TOTAL], L2[S::TOTAL];
+  double* const bufs[3] = {L0, L1, L2};
   const Geo& G = a.G;
   int bx, by, k;
   if (!plane_tile(a, blockIdx.x, bx, by, k)) return;  // whole workgroup: no barrier yet
@@ -110,8 +111,8 @@ __global__ void __launch_bounds__(TX * TY) bssn_hi_kernel(BssnArgs a) {
   const int x0 = bx * TX, y0 = by * TY;
   const int i = x0 + tx, j = y0 + ty;
   const bool active = i < G.n[0] && j < G.n[1];
-  HSrc<TX, TY, R> src;
-  src.init(G, a.io.yin, L0, L1, tab, x0, y0, k, tx, ty);
+  AHSrc<TX, TY, R, 3> src;
+  src.init(G, a.io.yin, bufs, x0, y0, k, tx, ty);
   T rhs[V_N];
   bssn_rhs_point<T, KO_OFF, ORD>(src, a.W, a.P, rhs);
   if (active)

@@ -406,4 +406,117 @@ struct ASrc {
   }
 };
 
+// Asynchronous staging of the 6th- and 8th-order neighbourhood (HShape):
+// the same copy scheme as ASrc (each lane copies a pair of doubles straight
+// into LDS; NBUF separate buffers, NBUF - 1 grid functions in flight; the
+// hand-off is a vmcnt wait plus a barrier), with HShape's plane layout and
+// accessor.  Pairs never straddle a row: every row length is even.
+template <int TX, int TY, int R, int NBUF>
+struct AHSrc {
+  using S = HShape<TX, TY, R>;
+  static constexpr int PAIRS = S::TOTAL / 2;
+  static constexpr int PSLOTS = (PAIRS + S::NT - 1) / S::NT;
+  static constexpr int D = NBUF - 1;
+  static_assert(S::TOTAL % 2 == 0 && S::W0 % 2 == 0 && S::W1 % 2 == 0 && TX % 2 == 0 &&
+                    S::N0 % 2 == 0 && S::N1 % 2 == 0,
+                "pairs must not straddle rows");
+  double* buf[NBUF];
+  const char* Yb;        // state allocation (byte address)
+  const double* Yc;      // centre value of variable 0 at the thread's (clamped) point
+  long long sv;          // elements between grid functions
+  unsigned off[PSLOTS];  // byte offset from Yb of each pair slot (variable 0)
+  int b0o, b1o, b3o;
+  int seq;
+  int wbase;             // 64 * wave index
+
+  __device__ __forceinline__ void init(const Geo& G, const double* yin, double* const* shared,
+                                       int x0, int y0, int k, int tx, int ty) {
+#pragma unroll
+    for (int b = 0; b < NBUF; ++b) buf[b] = shared[b];
+    Yb = reinterpret_cast<const char*>(yin);
+    sv = G.sv;
+    const int tid = ty * TX + tx;
+    wbase = tid & ~63;
+#pragma unroll
+    for (int m = 0; m < PSLOTS; ++m) {
+      int p = tid + m * S::NT;
+      if (p >= PAIRS) p = 0;  // masked off at issue
+      const int t = 2 * p;
+      int px, py, dz;
+      if (t < S::N0) {
+        dz = 0;
+        py = t / S::W0 - R;
+        px = t % S::W0 - R;
+      } else if (t < S::N0 + S::NMID * S::N1) {
+        const int r = t - S::N0, sgm = r / S::N1, q = r % S::N1;
+        dz = sgm < R - 1 ? sgm + 1 : -(sgm - (R - 1) + 1);
+        py = q / S::W1 - (R - 1);
+        px = q % S::W1 - (R - 1);
+      } else {
+        const int r = t - S::N0 - S::NMID * S::N1, sgm = r / S::N3, q = r % S::N3;
+        dz = sgm == 0 ? R : -R;
+        py = q / TX;
+        px = q % TX;
+      }
+      // pair start in [-g-1, n+g-1] keeps both doubles inside the padded row
+      int gx = x0 + px, gy = y0 + py;
+      gx = gx < -G.g - 1 ? -G.g - 1 : (gx > G.n[0] + G.g - 1 ? G.n[0] + G.g - 1 : gx);
+      gy = gy < -G.g ? -G.g : (gy > G.n[1] + G.g - 1 ? G.n[1] + G.g - 1 : gy);
+      off[m] = (unsigned)(8 * (G.off0 + gx + (long long)gy * G.sy + (long long)(k + dz) * G.sz));
+    }
+    b0o = ty * S::W0 + tx;
+    b1o = S::N0 + ty * S::W1 + tx;
+    b3o = S::N0 + S::NMID * S::N1 + ty * TX + tx;
+    const int ci = x0 + tx < G.n[0] ? x0 + tx : G.n[0] - 1;
+    const int cj = y0 + ty < G.n[1] ? y0 + ty : G.n[1] - 1;
+    Yc = yin + G.off0 + ci + (long long)cj * G.sy + (long long)k * G.sz;
+    seq = 0;
+  }
+
+  // start copying grid function kRhsOrder[s] into buffer s % NBUF
+  __device__ __forceinline__ void issue(int s) {
+    const char* base = Yb + (long long)RhsOrder::at(s) * sv * 8;
+    double* dst = buf[s % NBUF];
+    const int lane = (int)threadIdx.x & 63;
+#pragma unroll
+    for (int m = 0; m < PSLOTS; ++m) {
+      if (m < PSLOTS - 1 || wbase + lane + m * S::NT < PAIRS) {
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)(base + off[m]),
+                                         (lds_void_t*)(dst + 2 * (m * S::NT + wbase)), 16, 0, 0);
+      }
+    }
+  }
+
+  __device__ __forceinline__ double center(int v) const { return Yc[v * sv]; }
+
+  template <int YOUNGER>
+  __device__ __forceinline__ void wait_and_sync() {
+    wait_vm_lgkm0<YOUNGER * (PSLOTS - 1)>();
+    fence_memory();
+    __builtin_amdgcn_s_barrier();
+    fence_memory();
+  }
+
+  __device__ __forceinline__ HAcc<TX, TY, R> acquire(int /*v*/) {
+    if (seq == 0) {
+      fence_memory();
+#pragma unroll
+      for (int s = 0; s < D; ++s) issue(s);
+    }
+    const int last = seq + D - 1 < RhsOrder::N - 1 ? seq + D - 1 : RhsOrder::N - 1;
+    switch (last - seq) {  // folds to one case once seq is known
+      case 0: wait_and_sync<0>(); break;
+      case 1: wait_and_sync<1>(); break;
+      case 2: wait_and_sync<2>(); break;
+      case 3: wait_and_sync<3>(); break;
+      case 4: wait_and_sync<4>(); break;
+      default: wait_and_sync<5>(); break;
+    }
+    if (seq + D < RhsOrder::N) issue(seq + D);
+    double* b = buf[seq % NBUF];
+    ++seq;
+    return HAcc<TX, TY, R>{b + b0o, b + b1o, b + b3o};
+  }
+};
+
 }  // namespace chemora
