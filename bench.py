@@ -131,7 +131,7 @@ def main(argv=None) -> int:
                     help="time only the FP64 right-hand side (for profiler runs)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU halo exchange is a design, not an implementation", file=sys.stderr)
         return 2
 
