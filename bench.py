@@ -67,6 +67,24 @@ def _events_time(fn, reps):
     return start.elapsed_time(stop) / 1e3 / reps
 
 
+def _high_order_times(C, torch, n, h, y0, kw):
+    """6th- and 8th-order right-hand sides at n^3 (staged high-order kernel),
+    FP64 and mixed: kernel milliseconds from HIP events, 10 launches each."""
+    khi = {}
+    for order in (6, 8):
+        gho = order // 2 + 1
+        for name, prec in (("fp64", C.FP64), ("mixed", C.MIXED)):
+            go = C.Grid((n, n, n), gho, h, precision=prec, fd_order=order, **kw)
+            so = go.upload(y0)
+            go.fill_ghosts(so)
+            ro = go.new_state()
+            go.rhs(so, ro)
+            khi[f"bssn_rhs_order{order}_{name}"] = _events_time(lambda: go.rhs(so, ro), 10) * 1e3
+            del go, so, ro
+    torch.cuda.synchronize()
+    return khi
+
+
 def _amr_timing(C, torch):
     """Prolongation (three coarse time levels) and restriction between a 128^3
     BSSN level and a centred 96^3 fine patch, 24 grid functions; algorithmic
@@ -127,6 +145,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-patch batch timing")
     ap.add_argument("--only-wave", action="store_true",
                     help="time only the 256^3 wave RK4 steps and the copy (for profiler runs)")
+    ap.add_argument("--only-hi", action="store_true",
+                    help="time only the 6th/8th-order right-hand sides (for profiler runs)")
     ap.add_argument("--only-rhs", action="store_true",
                     help="time only the FP64 right-hand side (for profiler runs)")
     args = ap.parse_args(argv)
@@ -195,6 +215,9 @@ def main(argv=None) -> int:
     reps = max(args.steps, 20)
     k64 = _events_time(lambda: g64.rhs(st, rhs), reps)
     kghost = _events_time(lambda: g64.fill_ghosts(st), reps)
+    if args.only_hi:
+        print(json.dumps(_high_order_times(C, torch, n, h, y0, kw)))
+        return 0
     if args.only_rhs:
         # plus a streaming copy of known size: the calibration kernel for
         # hardware byte counters collected on this same command
@@ -220,19 +243,7 @@ def main(argv=None) -> int:
     kmx = _events_time(lambda: gmx.rhs(st, rhs), reps)
     print(f"[bench] mixed step {elapsed_mx / args.steps * 1e3:.3f} ms", file=sys.stderr, flush=True)
 
-    # 6th- and 8th-order right-hand sides (cached-load kernels), FP64 and mixed
-    khi = {}
-    for order in (6, 8):
-        gho = order // 2 + 1
-        for name, prec in (("fp64", C.FP64), ("mixed", C.MIXED)):
-            go = C.Grid((n, n, n), gho, h, precision=prec, fd_order=order, **kw)
-            so = go.upload(y0)
-            go.fill_ghosts(so)
-            ro = go.new_state()
-            go.rhs(so, ro)
-            khi[f"bssn_rhs_order{order}_{name}"] = _events_time(lambda: go.rhs(so, ro), 10) * 1e3
-            del go, so, ro
-    torch.cuda.synchronize()
+    khi = _high_order_times(C, torch, n, h, y0, kw)
 
     # constraints (FP64 in both modes)
     hm_norms = torch.zeros(4, dtype=torch.float64, device="cuda")
