@@ -69,7 +69,8 @@ def _events_time(fn, reps):
 
 def _high_order_times(C, torch, n, h, y0, kw):
     """6th- and 8th-order right-hand sides at n^3 (staged high-order kernel),
-    FP64 and mixed: kernel milliseconds from HIP events, 10 launches each."""
+    FP64 and mixed, and the FP64 constraints at those orders: milliseconds from
+    HIP events, 10 launches each."""
     khi = {}
     for order in (6, 8):
         gho = order // 2 + 1
@@ -80,6 +81,13 @@ def _high_order_times(C, torch, n, h, y0, kw):
             ro = go.new_state()
             go.rhs(so, ro)
             khi[f"bssn_rhs_order{order}_{name}"] = _events_time(lambda: go.rhs(so, ro), 10) * 1e3
+            if prec == C.FP64:
+                nrm = torch.zeros(4, dtype=torch.float64, device="cuda")
+                cw = torch.empty(max(C.lib().chemora_constraints_workspace_bytes(go.handle) // 8,
+                                     1), dtype=torch.float64, device="cuda")
+                go.constraints(so, norms=nrm, workspace=cw)
+                khi[f"constraints_order{order}_fp64"] = _events_time(
+                    lambda: go.constraints(so, norms=nrm, workspace=cw), 10) * 1e3
             del go, so, ro
     torch.cuda.synchronize()
     return khi

@@ -193,6 +193,57 @@ __global__ void __launch_bounds__(TX * TY) constraints_async_kernel(ConsArgs a) 
   if (threadIdx.x < 4) a.partial[4LL * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// 6th- and 8th-order constraints: the same tiling with the wider staged
+// neighbourhood of those orders (HSrc: two buffers, one barrier per grid
+// function, any acquisition order)
+template <int TX, int TY, int ORD>
+__global__ void __launch_bounds__(TX * TY) constraints_hi_kernel(ConsArgs a) {
+  constexpr int R = ORD / 2 + 1;
+  using S = HShape<TX, TY, R>;
+  constexpr int NT = TX * TY;
+  __shared__ double L0[S::TOTAL], L1[S::TOTAL];
+  __shared__ int tab[S::TOTAL];
+  __shared__ double red[4][NT];
+  const Geo& G = a.G;
+  int bx, by, k;
+  bool has;
+  if (a.cols[0] > 0) {
+    has = column_tile(blockIdx.x, a.tiles, a.cols[0], a.cols[1], bx, by, k);
+  } else {
+    const int t = xcd_tile(blockIdx.x, a.tiles[0] * a.tiles[1] * a.tiles[2]);
+    bx = t % a.tiles[0];
+    by = (t / a.tiles[0]) % a.tiles[1];
+    k = t / (a.tiles[0] * a.tiles[1]);
+    has = true;
+  }
+  if (!has) {  // whole workgroup, before any barrier
+    if (threadIdx.x < 4) a.partial[4LL * blockIdx.x + threadIdx.x] = 0.0;
+    return;
+  }
+  const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
+  const int x0 = bx * TX, y0 = by * TY;
+  const int i = x0 + tx, j = y0 + ty;
+  const bool active = i < G.n[0] && j < G.n[1];
+  HSrc<TX, TY, R> src;
+  src.init(G, a.y, L0, L1, tab, x0, y0, k, tx, ty);
+  double c[4];
+  constraints_point<ORD>(src, a.W, c);
+  const long long p = i + (long long)j * G.sy + (long long)k * G.sz;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (a.hm && active) a.hm[G.off0 + p + q * G.sv] = c[q];
+    red[q][threadIdx.x] = active ? c[q] * c[q] : 0.0;
+  }
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) a.partial[4LL * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
 // Sum the per-workgroup partials in a fixed order and take sqrt(sum / N).
 __global__ void __launch_bounds__(CT) norms_kernel(const double* partial, int nb, double npts,
                                                    double* norms) {
@@ -232,10 +283,11 @@ bool staged() {
   return v;
 }
 
-// returns the number of workgroups (the staged kernel exists for order 4)
+// returns the number of workgroups
 long long plan(const Geo& G, int order, ConsArgs& a) {
   a.cols[0] = a.cols[1] = 0;
-  if (staged() && order == 4) {
+  (void)order;
+  if (staged()) {
     a.ltx = G.n[0] >= 24 ? 32 : 16;
     a.lty = CT / a.ltx;
     a.tiles[0] = (G.n[0] + a.ltx - 1) / a.ltx;
@@ -279,10 +331,18 @@ hipError_t launch_bssn_constraints(const Geo& G, const BssnPar& P, const double*
   a.hm = hm;
   a.partial = partial;
   const int nb = (int)plan(G, P.fd_order, a);
-  if (P.fd_order == 6)
+  if (P.fd_order == 6 && !staged())
     hipLaunchKernelGGL(constraints_kernel<6>, dim3(nb), dim3(CT), 0, s, a);
-  else if (P.fd_order == 8)
+  else if (P.fd_order == 8 && !staged())
     hipLaunchKernelGGL(constraints_kernel<8>, dim3(nb), dim3(CT), 0, s, a);
+  else if (P.fd_order == 6 && a.ltx == 32)
+    hipLaunchKernelGGL((constraints_hi_kernel<32, 8, 6>), dim3(nb), dim3(CT), 0, s, a);
+  else if (P.fd_order == 6)
+    hipLaunchKernelGGL((constraints_hi_kernel<16, 16, 6>), dim3(nb), dim3(CT), 0, s, a);
+  else if (P.fd_order == 8 && a.ltx == 32)
+    hipLaunchKernelGGL((constraints_hi_kernel<32, 8, 8>), dim3(nb), dim3(CT), 0, s, a);
+  else if (P.fd_order == 8)
+    hipLaunchKernelGGL((constraints_hi_kernel<16, 16, 8>), dim3(nb), dim3(CT), 0, s, a);
   else if (!staged())
     hipLaunchKernelGGL(constraints_kernel<4>, dim3(nb), dim3(CT), 0, s, a);
   else if (a.ltx == 32 && cons_nbuf() == 6)

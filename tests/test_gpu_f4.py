@@ -59,8 +59,9 @@ def test_rk4_high_order(order, bc):
 
 
 @pytest.mark.parametrize("order", [6, 8])
-def test_constraints_high_order(order):
-    n = (30, 17, 12)
+@pytest.mark.parametrize("n", [(30, 17, 12), (20, 18, 11)])
+def test_constraints_high_order(order, n):
+    """staged 32 x 8 (n_x >= 24) and 16 x 16 tiles, both ragged"""
     h = tuple(1.0 / v for v in n)
     gr, b = pair(n, order // 2 + 1, h, C.BSSN, fd_order=order)
     y0 = _smooth_random(n, 12)
@@ -73,6 +74,6 @@ def test_constraints_high_order(order):
     oracle.fill_periodic(b, yo)
     hmo, no = oracle.constraints(b, yo)
     e = parity(gr.download(hm, nvars=4), b.interior(hmo))
-    print("constraints order", order, e, norms.cpu().numpy(), no)
+    print("constraints order", order, n, e, norms.cpu().numpy(), no, flush=True)
     assert e.max() <= 1e-12
     assert np.allclose(norms.cpu().numpy(), no, rtol=1e-12, atol=0)
