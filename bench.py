@@ -153,6 +153,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-patch batch timing")
     ap.add_argument("--only-wave", action="store_true",
                     help="time only the 256^3 wave RK4 steps and the copy (for profiler runs)")
+    ap.add_argument("--only-amr", action="store_true",
+                    help="time only prolongation and restriction (for profiler runs)")
     ap.add_argument("--only-hi", action="store_true",
                     help="time only the 6th/8th-order right-hand sides (for profiler runs)")
     ap.add_argument("--only-rhs", action="store_true",
@@ -170,6 +172,18 @@ def main(argv=None) -> int:
     from paper_1410_1764_amd import inputs as I
 
     torch.cuda.set_device(0)
+    if args.only_amr:
+        # plus the streaming copy: the calibration kernel for byte counters
+        nb = 1 << 29
+        a = torch.empty(nb // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        C.probe_copy(b, a, nb)
+        kc = _events_time(lambda: C.probe_copy(b, a, nb), 10)
+        del a, b
+        out = _amr_timing(C, torch)
+        out["copy_512MiB_ms"] = kc * 1e3
+        print(json.dumps(out))
+        return 0
     if args.only_wave:
         nw = 256
         hw = 1.0 / nw
