@@ -28,10 +28,13 @@ What each routine follows in the paper (arXiv:1410.1764):
     interpolation into fine ghost zones; injection back onto the coarse level.
 
 Parity status of each routine (pins in ``tests/test_oracle_*.py``): all are
-pinned to closed forms, convergence orders or invariants, except the 1+log /
-Gamma-driver gauge right-hand sides (alpha, beta, B), which are definitions
-with no exact solution to compare against: parity unpinned beyond constraint
-convergence and agreement with the GPU path.
+pinned to closed forms, convergence orders or invariants.  The 1+log /
+harmonic lapse and Gamma-driver shift right-hand sides are pinned on data
+with closed-form derivatives (sheared moving coordinates and a constant
+shift, with smooth lapse, K and B^i): 4th-order convergence to the
+definitions evaluated with exact derivatives, and every plausible sign,
+coefficient or missing-term mistake misses them by far more than that
+(``tests/test_oracle_gauge.py``).
 """
 from __future__ import annotations
 

@@ -15,8 +15,8 @@ mathematical property:
   * Hamiltonian / momentum constraints vanish at 4th order on exact data;
   * harmonic gauge-wave evolution converges to the exact solution at 4th
     order; under 1+log / Gamma-driver the Hamiltonian constraint converges.
-The 1+log / Gamma-driver gauge right-hand sides themselves are definitions
-with no exact solution: parity unpinned beyond these checks.
+The 1+log / Gamma-driver gauge right-hand sides are pinned separately on
+closed-form data in test_oracle_gauge.py.
 """
 import numpy as np
 import pytest
