@@ -109,7 +109,8 @@ typedef struct {
                         right-hand side of every evolved variable; 0 = off; order 4 only */
   int32_t fd_order;  /* finite-difference order (Sec. III.B.2: the order is a parameter of
                         the discretisation): 0 or 4 (default), or 6 or 8 for BSSN, which
-                        needs ghost >= fd_order/2 + 1 and runs the cached-load kernels */
+                        needs ghost >= fd_order/2 + 1 and runs the LDS-staged high-order
+                        kernels (the cached-load ones are an ablation switch) */
 } chemora_grid_desc;
 
 /* Create a grid object from a description (copied).  Validates every field
@@ -148,8 +149,10 @@ int chemora_rhs(chemora_grid* grid, const double* state, double* rhs, chemora_st
 
 /* Advance state by nsteps classical RK4 steps of size dt starting at time t
  * (Sec. II: the time-integrator thorn).  Ghosts are refilled before every
- * right-hand-side evaluation -- periodic ghosts are written by the kernel
- * that produces each stage; analytic ghosts use the stage time
+ * right-hand-side evaluation -- periodic ghosts by a fill kernel launched
+ * after each substage's kernel (the environment switch
+ * CHEMORA_PERIODIC=images makes the substage kernel write the images
+ * itself); analytic ghosts use the stage time
  * t_n + c_s dt, c = (0, 1/2, 1/2, 1) -- and are valid on return at time
  * t + nsteps*dt.  workspace: chemora_workspace_bytes(grid) bytes, contents
  * ignored.  BC_CALLER is rejected (CHEMORA_ERR_INVALID). */

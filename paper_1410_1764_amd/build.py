@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libchemora.so")
-SOURCES = ["api.cpp", "ghost.hip", "wave.hip", "wave5.hip", "bssn.hip", "constraints.hip", "batch.hip",
+SOURCES = ["api.cpp", "ghost.hip", "wave.hip", "wave5.hip", "bssn.hip", "bssn_split.hip", "constraints.hip", "batch.hip",
            "amr.hip", "probe.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

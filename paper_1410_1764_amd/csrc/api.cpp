@@ -286,7 +286,10 @@ int chemora_rk4_step(chemora_grid* grid, double* state, void* workspace, double 
     double* ins[5] = {nullptr, state, B1, B2, B1};
     double* outs[5] = {nullptr, B1, B2, B1, state};
     for (int stage = 1; stage <= 4; ++stage) {
-      StageIO io{ins[stage], state, acc, outs[stage], cdt[stage]};
+      // the last stage writes the state itself, which it also reads
+      // pointwise as y_n: B2, free by then, takes the split kernels'
+      // intermediates
+      StageIO io{ins[stage], state, acc, outs[stage], cdt[stage], stage == 4 ? B2 : nullptr};
       st = device_status(launch_stage(grid, stage, images, io, s), "RK4 substage launch");
       if (st != CHEMORA_OK) return st;
       if (periodic && !images) {

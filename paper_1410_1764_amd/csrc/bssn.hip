@@ -16,31 +16,10 @@
 #include <cstdlib>
 #include <cstring>
 
-#include "bssn_lds.h"
+#include "bssn_args.h"
 
 namespace chemora {
 namespace {
-
-struct BssnArgs {
-  Geo G;
-  BssnPar P;
-  Weights W;
-  StageIO io;
-  int ltx, lty, zc;
-  int tiles[3];
-  int cols[2];  // column split of the staged kernels (column_tile); 0: xcd_tile order
-  int images;
-};
-
-// tile of workgroup b in the single-plane (staged) kernels
-__device__ __forceinline__ bool plane_tile(const BssnArgs& a, int b, int& bx, int& by, int& bz) {
-  if (a.cols[0] > 0) return column_tile(b, a.tiles, a.cols[0], a.cols[1], bx, by, bz);
-  const int t = xcd_tile(b, a.tiles[0] * a.tiles[1] * a.tiles[2]);
-  bx = t % a.tiles[0];
-  by = (t / a.tiles[0]) % a.tiles[1];
-  bz = t / (a.tiles[0] * a.tiles[1]);
-  return true;
-}
 
 // CHEMORA_BSSN_WAVES: minimum waves per SIMD the register allocator must
 // allow (an ablation switch; 1 lets the FP64 kernel use VGPRs + AGPRs).
@@ -331,6 +310,9 @@ hipError_t launch_bssn_stage(const Geo& G, const BssnPar& P, int stage, int prec
     }
   }
   const dim3 grid((unsigned)blocks);
+  hipError_t err = hipSuccess;
+  if (kernel_variant(precision) == 2 && launch_bssn_split(stage, precision, a, grid, s, &err))
+    return err;
   return precision == CHEMORA_MIXED ? launch_t<float>(stage, a, grid, s)
                                     : launch_t<double>(stage, a, grid, s);
 }

@@ -49,6 +49,11 @@ struct StageIO {
   double* acc;        // accumulator (pointwise)
   double* out;        // stage output, or the rhs for stage 0
   double cdt;         // dt/2, dt/2, dt, dt/6 for stages 1..4
+  // Split kernels only: a state-sized buffer whose interior holds the
+  // first kernel's per-point intermediates until the second kernel reads
+  // them (each point's own values, read before that point is written).
+  // nullptr: out serves (it may not when out aliases y0, the last stage).
+  double* tmp = nullptr;
 };
 
 // Hardware places workgroup b on XCD b % 8.  Give each XCD a contiguous range

@@ -1,14 +1,23 @@
-"""The two larger workloads as parity cases, at their full sizes:
+"""The two larger workloads as parity cases, at their full sizes and their
+configured step counts:
 
-* BSSN at 192^3 + 3 ghosts, gauge-wave data (A = 0.1), 1+log / Gamma-driver,
-  periodic, 50 RK4 steps in mixed precision: one FP64 step against the
-  oracle, then the mixed evolution against the FP64 one after all 50 steps
-  (<= 1e-5 per grid function), with the FP64 constraint norms of both;
+* BSSN at 192^3 + 3 ghosts, gauge-wave data (A = 0.1, along x), 1+log /
+  Gamma-driver, periodic, 50 RK4 steps, FP64 and mixed: every point of both
+  evolutions against the oracle after all 50 steps (FP64 <= 1e-12, mixed
+  <= 1e-5 per grid function; the mixed error also in the increment-relative
+  form), with the FP64 constraint norms of both.  The data depend on x
+  alone, so the oracle's 3-D evolution is the evolution of a 192 x 4 x 4
+  periodic box (same spacing on every axis) repeated along y and z, bit for
+  bit: every point computes the same operations on the same values, and
+  differences across y and z are exactly zero (pinned on the CPU in
+  test_oracle_configs.py);
 * 64 uneven patches (sizes 24..96 per axis, three refinement levels,
   analytic gauge-wave ghosts at every substage) advanced by the batched,
   graph-captured path with autotuned tiles, FP64 and mixed: every patch
-  against an oracle run of that patch alone after 2 steps, then mixed
-  against FP64 after 20 steps.
+  against an oracle run of that patch alone after all 20 steps.  Pure gauge
+  wave, as configured: the off-diagonal components are zero but for
+  boundary mismatches of the analytic ghosts, so they are measured against
+  the size of their tensor (helpers.parity_tensor).
 """
 import numpy as np
 import pytest
@@ -17,85 +26,104 @@ import torch
 import oracle
 from paper_1410_1764_amd import chemora as C
 from paper_1410_1764_amd import inputs as I
-from tests.helpers import pair, parity
+from tests.helpers import increment_error, pair, parity_tensor
 from tests.test_gpu_batch import _patches
 
 pytestmark = pytest.mark.gpu
 
 
-def test_bssn_192_mixed_50_steps():
+def _line_errors(full, line, y0line=None):
+    """per grid function: max |full - line| over every point (line broadcast
+    along y and z) / max |line|; with y0line also the increment-relative
+    form.  full: (24, nz, ny, nx), line: (24, 1, 1, nx)."""
+    e = np.zeros(full.shape[0])
+    ei = np.zeros(full.shape[0])
+    for v in range(full.shape[0]):
+        d = np.abs(full[v] - line[v]).max()
+        s = np.abs(line[v]).max()
+        e[v] = d / s if s else (0.0 if np.abs(full[v]).max() == 0 else np.inf)
+        if y0line is not None:
+            inc = np.abs(line[v] - y0line[v]).max()
+            ei[v] = d / inc if inc else d
+    return e, ei
+
+
+def c3_oracle_line(n=192, steps=50):
+    """the oracle's 50-step state of the 192^3 workload, as one x line"""
+    h = 1.0 / n
+    b = oracle.Block((n, 4, 4), 3, (h, h, h), slicing=0, shift=1)
+    y0 = I.gaugewave((n, 4, 4), (h, h, h), A=0.1, d=1.0, axis=0)
+    y = b.embed(y0)
+    oracle.rk4(b, oracle.BSSN, oracle.BC_PERIODIC, y, 0.0, 0.25 * h, steps)
+    return b.interior(y)[:, :1, :1, :], y0[:, :1, :1, :]
+
+
+@pytest.mark.timeout(600)
+def test_bssn_192_fp64_and_mixed_50_steps_vs_oracle():
     n = (192, 192, 192)
     h = (1 / 192,) * 3
     kw = dict(slicing=0, shift=1)
-    g64, b = pair(n, 3, h, C.BSSN, precision=C.FP64, **kw)
+    g64, _ = pair(n, 3, h, C.BSSN, precision=C.FP64, **kw)
     gmx = C.Grid(n, 3, h, system=C.BSSN, precision=C.MIXED, **kw)
     y0 = I.gaugewave(n, h, A=0.1, d=1.0, axis=0)
     dt = 0.25 / 192
     s64, smx = g64.upload(y0), gmx.upload(y0)
+    del y0
     ws = g64.new_workspace()
-    # one FP64 step against the oracle
-    g64.rk4_step(s64, ws, 0.0, dt, 1)
-    torch.cuda.synchronize()
-    yo = b.embed(y0)
-    oracle.rk4(b, oracle.BSSN, oracle.BC_PERIODIC, yo, 0.0, dt, 1)
-    e = parity(g64.download(s64), b.interior(yo))
-    print("c3 fp64 step 1 vs oracle", e.max(), I.BSSN_NAMES[int(np.argmax(e))], flush=True)
-    assert e.max() <= 1e-12
-    del yo
-    # 50 steps: FP64 and mixed
-    g64.rk4_step(s64, ws, dt, dt, 49)
+    g64.rk4_step(s64, ws, 0.0, dt, 50)
     gmx.rk4_step(smx, ws, 0.0, dt, 50)
     torch.cuda.synchronize()
-    e = parity(gmx.download(smx), g64.download(s64))
-    print("c3 mixed vs fp64 after 50 steps, per grid function:",
-          {I.BSSN_NAMES[v]: float(e[v]) for v in range(len(e))}, flush=True)
-    assert e.max() <= 1e-5
+    print("c3: 50 steps done on the GPU", flush=True)
+    line, y0line = c3_oracle_line()
+    e64, _ = _line_errors(g64.download(s64), line)
+    print("c3 fp64 vs oracle after 50 steps, worst", e64.max(), I.BSSN_NAMES[int(np.argmax(e64))],
+          flush=True)
+    assert e64.max() <= 1e-12
+    emx, eimx = _line_errors(gmx.download(smx), line, y0line)
+    print("c3 mixed vs oracle after 50 steps, per grid function:",
+          {I.BSSN_NAMES[v]: float(emx[v]) for v in range(24)}, flush=True)
+    print("c3 mixed increment-relative error:",
+          {I.BSSN_NAMES[v]: float(eimx[v]) for v in range(24)}, flush=True)
+    assert emx.max() <= 1e-5
     # FP64 constraint norms of both evolutions (the mixed state is FP64)
     g64.fill_ghosts(s64)
-    gmx.fill_ghosts(smx)
+    g64.fill_ghosts(smx)
     n64 = g64.constraints(s64).cpu().numpy()
     nmx = g64.constraints(smx).cpu().numpy()
     print("c3 constraint norms (H, M1, M2, M3): fp64", n64, "mixed", nmx, flush=True)
+    # the mixed state carries FP32 rounding of every increment, which the
+    # second derivatives in H amplify by 1/h^2: reported, not compared
     assert np.all(np.isfinite(n64)) and np.all(np.isfinite(nmx))
 
 
-def test_batch_64_patches_fp64_and_mixed():
+@pytest.mark.timeout(900)
+def test_batch_64_patches_fp64_and_mixed_20_steps_vs_oracle():
     specs = [{"n": p["n"], "h": p["h"], "origin": p["origin"]}
              for p in I.patch_list(I.SEED0 + 4, 64, 24, 96)]
     dt = 0.25 * min(sp["h"] for sp in specs)
-    runs = {}
+    out = {}
     for prec in (C.FP64, C.MIXED):
-        grids, blocks, states, wss, y0s = _patches(specs, prec, seed=4)
+        grids, blocks, states, wss, y0s = _patches(specs, prec, pure=True)
         meta = torch.empty(C.batch_meta_bytes(len(grids)) // 8, dtype=torch.float64,
                            device="cuda")
         C.autotune(grids, states, wss, meta, None)
-        C.batch_step(grids, states, wss, meta, 0.0, dt, 2)
+        C.batch_step(grids, states, wss, meta, 0.0, dt, 20)
         torch.cuda.synchronize()
-        runs[prec] = (grids, blocks, states, wss, y0s, meta)
-        print("c4 precision", prec, "2 steps done", flush=True)
-    # FP64 and mixed against the oracle after 2 steps, patch by patch
-    grids, blocks, states, wss, y0s, meta = runs[C.FP64]
-    gmx, _, smx, _, _, _ = runs[C.MIXED]
-    worst64 = worstmx = 0.0
-    for q in range(len(grids)):
+        out[prec] = [g.download(s) for g, s in zip(grids, states)]
+        C.batch_release(meta)
+        del grids, states, wss, meta
+        torch.cuda.synchronize()
+        print("c4 precision", prec, "20 steps done", flush=True)
+    worst = {C.FP64: 0.0, C.MIXED: 0.0}
+    worst_inc = 0.0
+    for q in range(len(specs)):
         yo = blocks[q].embed(y0s[q])
-        oracle.rk4(blocks[q], oracle.BSSN, oracle.BC_GAUGEWAVE, yo, 0.0, dt, 2)
+        oracle.rk4(blocks[q], oracle.BSSN, oracle.BC_GAUGEWAVE, yo, 0.0, dt, 20)
         yi = blocks[q].interior(yo)
-        worst64 = max(worst64, parity(grids[q].download(states[q]), yi).max())
-        worstmx = max(worstmx, parity(gmx[q].download(smx[q]), yi).max())
-    print("c4 after 2 steps vs oracle: fp64", worst64, "mixed", worstmx, flush=True)
-    assert worst64 <= 1e-12
-    assert worstmx <= 1e-5
-    # 18 more steps each, then mixed against FP64
-    for prec in (C.FP64, C.MIXED):
-        g, _, s, w, _, m = runs[prec]
-        C.batch_step(g, s, w, m, 2 * dt, dt, 18)
-    torch.cuda.synchronize()
-    worst = 0.0
-    for q in range(len(grids)):
-        e = parity(gmx[q].download(smx[q]), grids[q].download(states[q]))
-        worst = max(worst, e.max())
-    print("c4 mixed vs fp64 after 20 steps:", worst, flush=True)
-    assert worst <= 1e-5
-    for prec in (C.FP64, C.MIXED):
-        C.batch_release(runs[prec][5])
+        for prec in (C.FP64, C.MIXED):
+            worst[prec] = max(worst[prec], parity_tensor(out[prec][q], yi).max())
+        worst_inc = max(worst_inc, increment_error(out[C.MIXED][q], yi, y0s[q]).max())
+    print("c4 after 20 steps vs oracle: fp64", worst[C.FP64], "mixed", worst[C.MIXED],
+          "mixed increment-relative", worst_inc, flush=True)
+    assert worst[C.FP64] <= 1e-12
+    assert worst[C.MIXED] <= 1e-5
