@@ -36,8 +36,14 @@ BSSN_BYTES_PER_PT = 24 * 8 * 2       # read every variable once, write every rhs
 # paper_1410_1764_amd/kernel_facts.json; the same file holds the HBM traffic
 # per launch measured with hardware counters, valid only while the hash of
 # the kernel sources matches.
-KERNEL_FP64 = "bssn_async_kernel<0,double,32,8,3,KO_OFF>"
-KERNEL_MIXED = "bssn_async_kernel<0,float,32,8,3,KO_OFF>"
+# The right-hand side that runs by default: FP64 as a pair of kernels
+# (curvature, then shift/advection/assembly; 32x8x2-point workgroups), mixed
+# as one fused kernel over the same z-blocked staging.  Its roofline counts
+# the method's operations (the fused FP64 kernel's static count; the pair
+# executes about 1 % more, recomputing the inverse metric) over the time of
+# the whole right-hand side.
+KERNEL_FP64 = "bssn_curv_kernel<double,KO_OFF> + bssn_rest_kernel<0,double,KO_OFF,8>"
+KERNEL_MIXED = "bssn_zfused_kernel<0,float,KO_OFF,8>"
 # Mixed precision runs unpacked FP32 (packed FP32 is disabled at compile
 # time), which issues at the FP64 vector rate: 256 CUs x 4 SIMDs x 16 lanes
 # x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s.
@@ -53,6 +59,18 @@ def _facts():
     tr = facts.get("traffic")
     facts["traffic_valid"] = bool(tr) and tr.get("source_hash") == isa_count.source_hash()
     return facts
+
+
+def _cpu_model() -> str:
+    """the host CPU's model name (first processor in /proc/cpuinfo)"""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _events_time(fn, reps):
@@ -264,6 +282,18 @@ def main(argv=None) -> int:
     value_mx = pts * args.steps / elapsed_mx
     kmx = _events_time(lambda: gmx.rhs(st, rhs), reps)
     print(f"[bench] mixed step {elapsed_mx / args.steps * 1e3:.3f} ms", file=sys.stderr, flush=True)
+    # mixed right-hand side against the FP64 one on the same state, per grid
+    # function (max |mixed - fp64| / max |fp64| over interior points); the
+    # comparisons with the CPU oracle itself are the parity tests'
+    rhs_mx = gmx.rhs(st)
+    g64.rhs(st, rhs)
+    mixed_err = {}
+    for v in range(24):
+        a64, amx = g64.view(rhs, v, ghosts=False), gmx.view(rhs_mx, v, ghosts=False)
+        scale = float(a64.abs().max())
+        d = float((amx - a64).abs().max())
+        mixed_err[I.BSSN_NAMES[v]] = d / scale if scale else d
+    del rhs_mx
 
     khi = _high_order_times(C, torch, n, h, y0, kw)
 
@@ -405,7 +435,7 @@ def main(argv=None) -> int:
             oracle.bssn_rhs(blk, yo)
         tc = (time.perf_counter() - t0) / reps_c
         cpu = {"value": nc ** 3 / tc, "unit": "grid-point updates/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
+               "cores": oracle.num_threads(), "cpu_model": _cpu_model(), "kind": "oracle",
                "sample": f"BSSN RHS on the {nc}^3 + 3-ghost gauge-wave block (1+log, "
                          f"Gamma-driver), mean of {reps_c} evaluations, {tc:.3f} s each"}
 
@@ -422,7 +452,9 @@ def main(argv=None) -> int:
         "roofline_other_bound": roof_other,
         "cpu_baseline": cpu,
         "mixed": {"value": value_mx, "ms_per_step": elapsed_mx / args.steps * 1e3,
-                  "dtype": "f32 arithmetic on f64 state", "roofline": roof_mx},
+                  "dtype": "f32 arithmetic on f64 state", "roofline": roof_mx,
+                  "rhs_error_vs_fp64_per_gf": mixed_err,
+                  "rhs_error_vs_fp64_max": max(mixed_err.values())},
         "kernels_ms": {"bssn_rhs_fp64": k64 * 1e3, "bssn_rhs_mixed": kmx * 1e3,
                        "ghost_periodic_24var": kghost * 1e3, "constraints_fp64": kcons * 1e3,
                        "bssn_rk4_step_fp64": krk64 * 1e3, "bssn_rk4_step_mixed": krkmx * 1e3,

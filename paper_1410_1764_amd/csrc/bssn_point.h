@@ -50,8 +50,9 @@ enum : int {
 // arithmetic producing it cannot sink below the next group's loads, which
 // in turn cannot rise above the memory fence.  No instruction is emitted.
 // CHEMORA_BSSN_FENCE selects the policy (an ablation switch; every level
-// computes the same values): 2 = fence after every stencil group (default),
-// 1 = fence once per grid function, 0 = no fences.
+// computes the same values): 3 = also after each mixed derivative (the
+// register-capped split kernels), 2 = fence after every stencil group
+// (default), 1 = fence once per grid function, 0 = no fences.
 #ifndef CHEMORA_BSSN_FENCE
 #define CHEMORA_BSSN_FENCE 2
 #endif
@@ -306,7 +307,15 @@ __device__ __forceinline__ void second_derivs(const Acc& f, const Weights& w, co
   dd[3] = d2pure[1];
   dd[5] = d2pure[2];
   dd[1] = mixed_deriv<T, ORD>(f, 0, 1, w.w11[0]);
+  if (CHEMORA_BSSN_FENCE >= 3) {
+    pin(dd[1]);
+    fence_memory();
+  }
   dd[2] = mixed_deriv<T, ORD>(f, 0, 2, w.w11[1]);
+  if (CHEMORA_BSSN_FENCE >= 3) {
+    pin(dd[2]);
+    fence_memory();
+  }
   dd[4] = mixed_deriv<T, ORD>(f, 1, 2, w.w11[2]);
   if (CHEMORA_BSSN_FENCE >= 1) {
     pin(dd[0]);
@@ -322,12 +331,13 @@ __device__ __forceinline__ void second_derivs(const Acc& f, const Weights& w, co
 // Geometry shared by the right-hand side and the constraints: inverse
 // conformal metric gu, Christoffels cdu (Gt^i_jk) and their contraction Gd,
 // d_i chi, and the Ricci tensor R_ij (conformal part + chi part).  With ADV
-// the advection terms of gt_ij, Gamt^i and chi are written to rhs as well.
-template <typename T, bool ADV, int KOM, int ORD, typename Src>
+// the advection terms of gt_ij, Gamt^i and chi are written to rhs[v] as
+// well (rhs: a T[V_N] array, or any object whose operator[] gives a T&).
+template <typename T, bool ADV, int KOM, int ORD, typename Src, typename Out>
 __device__ __forceinline__ void bssn_geometry(Src& src, const Weights& w, const bool bpos[3],
-                                              const T beta[3], T chi, const T gt[6], T gu[6],
+                                              const T beta[3], const T gt[6], T gu[6],
                                               T cdu[3][6], T Gd[3], T dchi[3], T R[6],
-                                              T rhs[V_N]) {
+                                              Out& rhs) {
   // ---- inverse conformal metric (adjugate / determinant)
   {
     const T c00 = gt[3] * gt[5] - gt[4] * gt[4];
@@ -429,6 +439,9 @@ __device__ __forceinline__ void bssn_geometry(Src& src, const Weights& w, const 
   // ---- chi: D_i D_j chi = d_i d_j chi - Gt^k_ij d_k chi; chi part of R_ij
   {
     const auto f = src.acquire(V_CHI);
+    // chi at the point, read from its own neighbourhood (the same value as
+    // the centre load), so that it is not held through the metric phase
+    const T chi = (T)f(0, 0, 0);
     axis_derivs<T, true, true, ADV, KOM, ORD>(f, w, bpos, beta, dchi, dpure, adv);
     if (ADV) rhs[V_CHI] = adv;
     second_derivs<T, ORD>(f, w, dpure, dd);
@@ -501,7 +514,7 @@ __device__ __forceinline__ void bssn_rhs_point(Src& src, const Weights& w, const
   }
 
   T gu[6], cdu[3][6], Gd[3], dchi[3], R[6];
-  bssn_geometry<T, true, KOM, ORD>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, rhs);
+  bssn_geometry<T, true, KOM, ORD>(src, w, bpos, beta, gt, gu, cdu, Gd, dchi, R, rhs);
   T dd[6], dpure[3], d1v[3], adv;
 
   // ---- lapse: D_i D_j alpha with the physical Christoffels

@@ -40,7 +40,7 @@ __device__ __forceinline__ void constraints_point(Src& src, const Weights& w, do
     At[q] = src.center(V_AT + q);
   }
   double gu[6], cdu[3][6], Gd[3], dchi[3], R[6], unused[V_N];
-  bssn_geometry<double, false, KO_OFF, ORD>(src, w, bpos, beta, chi, gt, gu, cdu, Gd, dchi, R, unused);
+  bssn_geometry<double, false, KO_OFF, ORD>(src, w, bpos, beta, gt, gu, cdu, Gd, dchi, R, unused);
   const double Rsc = chi * (gu[0] * R[0] + gu[3] * R[3] + gu[5] * R[5] +
                             2.0 * (gu[1] * R[1] + gu[2] * R[2] + gu[4] * R[4]));
   double Atm[3][3], Atu[6];

@@ -7,9 +7,13 @@ per grid point (plus a handful of index operations outside the point loop).
 FLOPs: v_fma/v_fmac = 2; add, sub, mul, ldexp (a multiply by a power of two),
 rcp and sqrt = 1; conversions and selects are not counted.
 
-Counts the default kernels (async-staged 32x8 tiles, three buffers, no
-dissipation, in FP64 and in mixed precision) and writes paper_1410_1764_amd/kernel_facts.json, which bench.py
-reads for the ALU roofline.  The same file carries the HBM traffic per launch
+Counts the fused single-plane kernels (async-staged 32x8 tiles, three
+buffers, no dissipation, in FP64 and in mixed precision): their count is the
+method's operations per point, the numerator of the ALU roofline.  Also
+counts the kernels that run by default (FP64: the split curvature + rest
+pair; mixed: the z-blocked fused kernel), whose instruction counts include
+what the split recomputes.  Writes paper_1410_1764_amd/kernel_facts.json,
+which bench.py reads for the ALU roofline.  The same file carries the HBM traffic per launch
 measured with hardware counters, keyed by a hash of the kernel sources so that
 a stale figure is not reported once the kernel has changed.
 Usage: python -m paper_1410_1764_amd.isa_count
@@ -34,7 +38,8 @@ OPS = {
 
 
 FACTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "kernel_facts.json")
-KERNEL_SOURCES = ("bssn.hip", "bssn_lds.h", "bssn_point.h", "internal.h")
+KERNEL_SOURCES = ("bssn.hip", "bssn_split.hip", "bssn_args.h", "bssn_zsrc.h", "bssn_lds.h",
+                  "bssn_point.h", "internal.h")
 
 
 def source_hash() -> str:
@@ -70,13 +75,17 @@ def count(body: str):
     return res
 
 
-def main():
+def _asm(src: str) -> str:
     os.makedirs(B.BUILD, exist_ok=True)
-    out_s = os.path.join(B.BUILD, "bssn_device.s")
+    out_s = os.path.join(B.BUILD, src.split(".")[0] + "_device.s")
     cmd = [B.HIPCC, *B.CFLAGS, "--offload-device-only", "-S", "-o", out_s,
-           os.path.join(B.CSRC, "bssn.hip")]
+           os.path.join(B.CSRC, src)]
     subprocess.check_call(cmd)
-    asm = open(out_s).read()
+    return open(out_s).read()
+
+
+def main():
+    asm = _asm("bssn.hip")
     result = {"source": "paper_1410_1764_amd/csrc/bssn.hip", "arch": B.ARCH,
               "command": "python -m paper_1410_1764_amd.isa_count"}
     for name, body in kernel_bodies(asm):
@@ -92,6 +101,20 @@ def main():
                                "instructions": {**c["f32"]["instructions"],
                                                 **c["f64"]["instructions"]},
                                "global_loads": c["global_load"], "scratch_ops": c["scratch"]}
+    # kernels of the default path (right-hand side only, no dissipation)
+    split = {}
+    for name, body in kernel_bodies(_asm("bssn_split.hip")):
+        c = count(body)
+        if "bssn_curv_kernelIdLi0E" in name:
+            split["fp64_curv"] = {"kernel": name, **c["f64"]}
+        if "bssn_rest_kernelILi0EdLi0ELi8E" in name:
+            split["fp64_rest"] = {"kernel": name, **c["f64"]}
+        if "bssn_zfused_kernelILi0EfLi0ELi8E" in name:
+            split["mixed_zfused"] = {"kernel": name, "f32": c["f32"], "f64": c["f64"]}
+    if "fp64_curv" in split and "fp64_rest" in split:
+        split["fp64_pair_flops_per_point"] = (split["fp64_curv"]["flops_per_point"] +
+                                              split["fp64_rest"]["flops_per_point"])
+    result["default_path"] = split
     result["source_hash"] = source_hash()
     path = FACTS
     old = {}

@@ -70,3 +70,16 @@ def increment_error(gpu: np.ndarray, orc: np.ndarray, y0: np.ndarray) -> np.ndar
         s = np.abs(d_orc).max()
         out[v] = e / s if s else e
     return out
+
+
+def increment_error_tensor(gpu: np.ndarray, orc: np.ndarray, y0: np.ndarray) -> np.ndarray:
+    """Per grid function: max |(gpu - y0) - (orc - y0)| divided by the
+    largest change max |orc - y0| of any component of the same BSSN tensor
+    (absolute where the whole tensor is unchanged)."""
+    out = np.zeros(gpu.shape[0])
+    for lo, hi in BSSN_TENSORS:
+        s = max(np.abs(orc[v] - y0[v]).max() for v in range(lo, hi))
+        for v in range(lo, hi):
+            e = np.abs(gpu[v] - orc[v]).max()
+            out[v] = e / s if s else e
+    return out

@@ -137,7 +137,7 @@ def test_batch_kernel_kinds_match_oracle(kind, precision, tol, monkeypatch):
         assert e.max() <= tol
 
 
-def test_batch_equals_single_grid_path_and_replays():
+def test_batch_equals_single_grid_path_and_replays(monkeypatch):
     grids, blocks, states, wss, y0s = _patches(SMALL, C.FP64)
     meta = torch.empty(C.batch_meta_bytes(len(grids)) // 8, dtype=torch.float64, device="cuda")
     dt = 0.25 / 256
@@ -146,11 +146,21 @@ def test_batch_equals_single_grid_path_and_replays():
     C.batch_step(grids, states, wss, meta, 2 * dt, dt, 2)
     torch.cuda.synchronize()
     for g, st, y0 in zip(grids, states, y0s):
-        s1 = g.upload(y0)
-        g.rk4_step(s1, g.new_workspace(), 0.0, dt, 4)
-        torch.cuda.synchronize()
-        a, b = g.download(st), g.download(s1)
-        assert np.abs(a - b).max() <= 1e-15 * np.abs(b).max()
+        a = g.download(st)
+        # the single-grid fused kernel runs the batch's point code: equal up
+        # to the last bit or so; the default single-grid path (the split pair
+        # in FP64) contracts other products into FMAs: rounding-level equal
+        for split, tol in (("0", 1e-15), (None, 1e-13)):
+            if split is None:
+                monkeypatch.delenv("CHEMORA_BSSN_SPLIT", raising=False)
+            else:
+                monkeypatch.setenv("CHEMORA_BSSN_SPLIT", split)
+            s1 = g.upload(y0)
+            g.rk4_step(s1, g.new_workspace(), 0.0, dt, 4)
+            torch.cuda.synchronize()
+            b = g.download(s1)
+            d, scale = float(np.abs(a - b).max()), float(np.abs(b).max())
+            assert d <= tol * scale, (split, d, scale)
     C.batch_release(meta)
 
 
