@@ -171,6 +171,19 @@ int64_t chemora_constraints_workspace_bytes(const chemora_grid* grid);
 int chemora_constraints(chemora_grid* grid, const double* state, double* hm, double* norms,
                         void* workspace, chemora_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation and results as chemora_constraints (bitwise), with the
+ * per-workgroup partial sums in a static device buffer of the library
+ * instead of a workspace.  Allocates nothing.  The buffer holds 2^20
+ * doubles per GPU (8 MiB, kept until the process ends); a grid whose
+ * chemora_constraints_workspace_bytes exceeds 8 MiB returns
+ * CHEMORA_ERR_INVALID before any launch.  Every call on one GPU shares that
+ * GPU's buffer: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller. */
+int chemora_constraints_noalloc(chemora_grid* grid, const double* state, double* hm,
+                                double* norms, chemora_stream stream);
+
 /* Fig. 1's "Energy" calculation for the first-order wave system (WAVE5):
  * eps = (rho^2 + v_i v_i)/2 at interior points, written to eps (a 1-variable
  * state, may be NULL), and the total sum(eps) h_x h_y h_z written to the

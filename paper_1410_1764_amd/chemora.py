@@ -72,6 +72,7 @@ def lib():
         "chemora_rk4_step": (ctypes.c_int, [_vp, _vp, _vp, dbl, dbl, i32, _vp]),
         "chemora_constraints_workspace_bytes": (i64, [_vp]),
         "chemora_constraints": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "chemora_constraints_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
         "chemora_energy_workspace_bytes": (i64, [_vp]),
         "chemora_energy": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "chemora_batch_meta_bytes": (i64, [i32]),
@@ -229,6 +230,12 @@ class Grid:
                                         _ptr(workspace), _stream(stream)))
         return norms
 
+
+    def constraints_noalloc(self, state, norms, hm=None, stream=None):
+        """chemora_constraints_noalloc: norms (device double[4]) is the caller's"""
+        check(lib().chemora_constraints_noalloc(self.handle, _ptr(state), _ptr(hm), _ptr(norms),
+                                                _stream(stream)))
+        return norms
 
     def energy(self, state, eps=None, total=None, workspace=None, stream=None):
         """Fig. 1's Energy calculation (WAVE5): total = sum(eps) h^3 (device)"""

@@ -50,6 +50,10 @@ const BssnPar& grid_par(const chemora_grid* g) { return g->par; }
 const chemora_grid_desc& grid_desc(const chemora_grid* g) { return g->d; }
 long long grid_state_elems(const chemora_grid* g) { return g->state_elems; }
 
+// constraints.hip: the static partial-sum buffer of chemora_constraints_noalloc
+long long constraints_static_capacity();
+hipError_t constraints_static_partials(double** out);
+
 }  // namespace chemora
 
 namespace {
@@ -327,6 +331,28 @@ int chemora_constraints(chemora_grid* grid, const double* state, double* hm, dou
     return fail(CHEMORA_ERR_INVALID, "misaligned pointer");
   return device_status(launch_bssn_constraints(grid->geo, grid->par, state, hm, norms,
                                                static_cast<double*>(workspace),
+                                               static_cast<hipStream_t>(stream)),
+                       "constraints launch");
+}
+
+int chemora_constraints_noalloc(chemora_grid* grid, const double* state, double* hm,
+                                double* norms, chemora_stream stream) {
+  if (!grid) return fail(CHEMORA_ERR_INVALID, "grid is NULL");
+  if (grid->d.system != CHEMORA_BSSN)
+    return fail(CHEMORA_ERR_UNSUPPORTED, "constraints exist for the BSSN system only");
+  if (!state || !norms) return fail(CHEMORA_ERR_INVALID, "state and norms must not be NULL");
+  if (!aligned(state) || (hm && !aligned(hm)) || (reinterpret_cast<uintptr_t>(norms) & 7u))
+    return fail(CHEMORA_ERR_INVALID, "misaligned pointer");
+  const long long need = constraints_partial_count(grid->geo, grid->par.fd_order);
+  if (need > constraints_static_capacity())
+    return fail(CHEMORA_ERR_INVALID,
+                "grid needs %lld partial sums; the static buffer holds %lld (use "
+                "chemora_constraints with a workspace)",
+                need, constraints_static_capacity());
+  double* partial = nullptr;
+  const int st = device_status(constraints_static_partials(&partial), "static scratch lookup");
+  if (st != CHEMORA_OK) return st;
+  return device_status(launch_bssn_constraints(grid->geo, grid->par, state, hm, norms, partial,
                                                static_cast<hipStream_t>(stream)),
                        "constraints launch");
 }

@@ -7,6 +7,7 @@
 //         - 2/3 gt^ij d_j K - 3/2 At^ij d_j chi / chi
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "bssn_lds.h"
 
@@ -356,6 +357,40 @@ hipError_t launch_bssn_constraints(const Geo& G, const BssnPar& P, const double*
   const double npts = (double)G.n[0] * G.n[1] * G.n[2];
   hipLaunchKernelGGL(norms_kernel, dim3(1), dim3(CT), 0, s, partial, nb, npts, norms);
   return hipGetLastError();
+}
+
+// ---- partial sums without a caller workspace ----------------------------
+// For callers that cannot allocate (graph capture, serving loops): the
+// per-workgroup partial sums of chemora_constraints_noalloc live in this
+// file-scope device array.  Every GPU the library runs on holds its own copy
+// until the process ends; every call on a GPU shares that GPU's copy, so
+// calls that overlap on one GPU race.  Nothing in it has to start at zero:
+// each workgroup of the constraint kernel writes its 4 partials (zeros when
+// the column walk gives it no tile) before the norms kernel reads them.
+constexpr long long kStaticPartials = 1LL << 20;  // doubles: 8 MiB per GPU
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kStaticPartials];
+
+long long constraints_static_capacity() { return kStaticPartials; }
+
+hipError_t constraints_static_partials(double** out) {
+  static std::mutex mu;
+  static double* ptrs[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptrs[dev]) {
+    // the array's name is a host-side stand-in: its address on this device
+    // (current here) comes from the runtime, once per device
+    double* p = nullptr;
+    e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
+  return hipSuccess;
 }
 
 }  // namespace chemora

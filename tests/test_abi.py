@@ -220,3 +220,17 @@ def test_level_pair_validation():
                   boundary=C.BC_CALLER)
     assert L.chemora_restrict(co.handle, ctypes.c_void_p(1 << 30), away.handle, fs,
                               None) == C.OK
+
+
+def test_constraints_noalloc_refuses_grids_beyond_its_buffer():
+    """checked on the host before any device call: a grid whose partial sums
+    exceed the static buffer (2^20 doubles) is refused with INVALID"""
+    n = (1024, 1024, 1024)
+    g = C.Grid(n, 3, 1.0 / 1024, system=C.BSSN)
+    need = C.lib().chemora_constraints_workspace_bytes(g.handle)
+    assert need > 8 * (1 << 20)
+    st = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced
+    nrm = ctypes.c_void_p(1 << 21)
+    rc = C.lib().chemora_constraints_noalloc(g.handle, st, None, nrm, None)
+    assert rc == C.ERR_INVALID
+    assert b"static buffer" in C.lib().chemora_last_error()
