@@ -377,6 +377,15 @@ def main(argv=None) -> int:
     kcopy = _events_time(lambda: C.probe_copy(b, a, nbytes), 10)
     copy_bw = 2 * nbytes / kcopy
     del a, b
+    # FMA throughput probe: the measured vector ALU rate, FP64 and unpacked FP32
+    probe_out = torch.empty(C.lib().chemora_probe_fma_bytes() // 8, dtype=torch.float64,
+                            device="cuda")
+    alu_probe = {}
+    for name, prec in (("fp64", C.FP64), ("fp32_unpacked", C.MIXED)):
+        fl_probe = C.probe_fma(prec, probe_out, 4096)
+        kfma = _events_time(lambda: C.probe_fma(prec, probe_out, 4096), 10)
+        alu_probe[name] = fl_probe / kfma
+    del probe_out
     torch.cuda.synchronize()
     print("[bench] gpu done", file=sys.stderr, flush=True)
 
@@ -403,7 +412,9 @@ def main(argv=None) -> int:
         roof_alu = {"bound": "alu", "achieved": f64 * pts / k64 / 1e12, "peak": FP64_PEAK / 1e12,
                     "unit": "TFLOP/s", "frac": f64 * pts / k64 / FP64_PEAK,
                     "traffic": traffic64, "kernel": KERNEL_FP64,
-                    "kernel_ms": k64 * 1e3, "flops_per_point": f64, "points_per_launch": pts}
+                    "kernel_ms": k64 * 1e3, "flops_per_point": f64, "points_per_launch": pts,
+                    "probe_peak": alu_probe["fp64"] / 1e12,
+                    "frac_of_probe": f64 * pts / k64 / alu_probe["fp64"]}
         if f64 * pts / FP64_PEAK > bytes_launch / HBM_PEAK:
             roof, roof_other = roof_alu, roof_hbm
         else:
@@ -415,6 +426,8 @@ def main(argv=None) -> int:
                        "frac": fmx * pts / kmx / UNPACKED_PEAK, "traffic": traffic_mx,
                        "kernel": KERNEL_MIXED, "kernel_ms": kmx * 1e3,
                        "flops_per_point": fmx, "points_per_launch": pts,
+                       "probe_peak": alu_probe["fp32_unpacked"] / 1e12,
+                       "frac_of_probe": fmx * pts / kmx / alu_probe["fp32_unpacked"],
                        "note": "f32 (unpacked) and f64 vector operations, both at 78.6 TFLOP/s"}
 
     # ---- CPU baseline: the oracle on the host cores (rank 0, N = 1 only)
@@ -465,7 +478,9 @@ def main(argv=None) -> int:
                     "wave256_rk4_point_steps_per_s_fp64": nw ** 3 / kw64,
                     "wave256_rk4_GBps_fp64": 272 * nw ** 3 / kw64 / 1e9,
                     "wave256_rk4_GBps_mixed": 272 * nw ** 3 / kwmx / 1e9,
-                    "copy_GBps": copy_bw / 1e9},
+                    "copy_GBps": copy_bw / 1e9,
+                    "fma_probe_TFLOPs_fp64": alu_probe["fp64"] / 1e12,
+                    "fma_probe_TFLOPs_fp32_unpacked": alu_probe["fp32_unpacked"] / 1e12},
         "batch64": batch or None,
         "amr": amr,
     }

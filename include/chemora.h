@@ -278,6 +278,17 @@ int chemora_restrict(const chemora_grid* coarse, double* coarse_state, const che
  * bandwidth. */
 int chemora_probe_copy(void* dst, const void* src, int64_t nbytes, chemora_stream stream);
 
+/* FMA throughput probe, the measured counterpart of the vector ALU peak:
+ * 8192 workgroups of 256 threads, each thread running 16 independent FMA
+ * chains for iters steps in FP64 (precision CHEMORA_FP64) or FP32 (
+ * CHEMORA_MIXED; FP32 as this library compiles it, unpacked).  out: device
+ * buffer of chemora_probe_fma_bytes() bytes (receives one value per thread,
+ * so that no FMA is eliminated).  *flops (host) receives the floating-point
+ * operations of the launch (2 per FMA).  Asynchronous on stream. */
+int64_t chemora_probe_fma_bytes(void);
+int chemora_probe_fma(int32_t precision, void* out, int32_t iters, double* flops,
+                      chemora_stream stream);
+
 /* Thread-local description of the last failure; never NULL. */
 const char* chemora_last_error(void);
 

@@ -82,6 +82,8 @@ def lib():
         "chemora_autotune": (ctypes.c_int, [ctypes.POINTER(Patch), i32, _vp, ctypes.c_char_p]),
         "chemora_batch_tile": (ctypes.c_int, [ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]),
         "chemora_probe_copy": (ctypes.c_int, [_vp, _vp, i64, _vp]),
+        "chemora_probe_fma_bytes": (i64, []),
+        "chemora_probe_fma": (ctypes.c_int, [i32, _vp, i32, ctypes.POINTER(dbl), _vp]),
         "chemora_prolong": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(dbl), i32,
                                            dbl, _vp, _vp, _vp]),
         "chemora_restrict": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -248,6 +250,14 @@ class Grid:
         check(lib().chemora_energy(self.handle, _ptr(state), _ptr(eps), _ptr(total),
                                    _ptr(workspace), _stream(stream)))
         return total
+
+
+def probe_fma(precision: int, out, iters: int, stream=None) -> float:
+    """launch the FMA throughput probe; returns the launch's flop count"""
+    fl = ctypes.c_double()
+    check(lib().chemora_probe_fma(int(precision), _ptr(out), int(iters), ctypes.byref(fl),
+                                  _stream(stream)))
+    return fl.value
 
 
 def probe_copy(dst, src, nbytes: int, stream=None):

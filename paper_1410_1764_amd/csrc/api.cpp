@@ -53,6 +53,9 @@ long long grid_state_elems(const chemora_grid* g) { return g->state_elems; }
 // constraints.hip: the static partial-sum buffer of chemora_constraints_noalloc
 long long constraints_static_capacity();
 hipError_t constraints_static_partials(double** out);
+// probe.hip: the FMA throughput probe
+long long probe_fma_threads();
+hipError_t launch_probe_fma(int precision, void* out, int iters, double* flops, hipStream_t s);
 
 }  // namespace chemora
 
@@ -388,6 +391,20 @@ int chemora_probe_copy(void* dst, const void* src, int64_t nbytes, chemora_strea
     return fail(CHEMORA_ERR_INVALID, "dst and src must be 16-byte aligned");
   return device_status(launch_probe_copy(dst, src, nbytes, static_cast<hipStream_t>(stream)),
                        "copy probe launch");
+}
+
+int64_t chemora_probe_fma_bytes(void) { return probe_fma_threads() * (int64_t)sizeof(double); }
+
+int chemora_probe_fma(int32_t precision, void* out, int32_t iters, double* flops,
+                      chemora_stream stream) {
+  if (!out || !flops) return fail(CHEMORA_ERR_INVALID, "out and flops must not be NULL");
+  if (!aligned(out)) return fail(CHEMORA_ERR_INVALID, "out must be 256-byte aligned");
+  if (precision != CHEMORA_FP64 && precision != CHEMORA_MIXED)
+    return fail(CHEMORA_ERR_INVALID, "precision must be CHEMORA_FP64 or CHEMORA_MIXED");
+  if (iters < 1) return fail(CHEMORA_ERR_INVALID, "iters must be >= 1");
+  return device_status(
+      launch_probe_fma(precision, out, iters, flops, static_cast<hipStream_t>(stream)),
+      "FMA probe launch");
 }
 
 // Two refinement levels: checks the pair and returns the fine origin's

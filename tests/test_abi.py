@@ -234,3 +234,17 @@ def test_constraints_noalloc_refuses_grids_beyond_its_buffer():
     rc = C.lib().chemora_constraints_noalloc(g.handle, st, None, nrm, None)
     assert rc == C.ERR_INVALID
     assert b"static buffer" in C.lib().chemora_last_error()
+
+
+def test_probe_fma_validation():
+    L = C.lib()
+    fl = ctypes.c_double()
+    assert L.chemora_probe_fma_bytes() == 8192 * 256 * 8
+    assert L.chemora_probe_fma(C.FP64, None, 4, ctypes.byref(fl), None) == C.ERR_INVALID
+    assert L.chemora_probe_fma(C.FP64, ctypes.c_void_p(8), 4, ctypes.byref(fl), None) \
+        == C.ERR_INVALID
+    assert "aligned" in C.last_error()
+    assert L.chemora_probe_fma(7, ctypes.c_void_p(4096), 4, ctypes.byref(fl), None) \
+        == C.ERR_INVALID
+    assert L.chemora_probe_fma(C.FP64, ctypes.c_void_p(4096), 0, ctypes.byref(fl), None) \
+        == C.ERR_INVALID
