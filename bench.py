@@ -42,6 +42,11 @@ BSSN_BYTES_PER_PT = 24 * 8 * 2       # read every variable once, write every rhs
 # the method's operations (the fused FP64 kernel's static count; the pair
 # executes about 1 % more, recomputing the inverse metric) over the time of
 # the whole right-hand side.
+# The method's own count: the oracle's right-hand-side expression traced at
+# one point, common subexpressions merged (tests/flops/oracle_flops.cpp;
+# 1,953 stencil + 2,295 pointwise operations at 4th order, 1+log,
+# Gamma-driver), stated beside the instruction-stream count.
+FLOPS_PER_POINT_EXPRESSION = 4248
 KERNEL_FP64 = "bssn_curv_kernel<double,KO_OFF> + bssn_rest_kernel<0,double,KO_OFF,8>"
 KERNEL_MIXED = "bssn_zfused_kernel<0,float,KO_OFF,8>"
 # Mixed precision runs unpacked FP32 (packed FP32 is disabled at compile
@@ -413,6 +418,7 @@ def main(argv=None) -> int:
                     "unit": "TFLOP/s", "frac": f64 * pts / k64 / FP64_PEAK,
                     "traffic": traffic64, "kernel": KERNEL_FP64,
                     "kernel_ms": k64 * 1e3, "flops_per_point": f64, "points_per_launch": pts,
+                    "flops_per_point_expression": FLOPS_PER_POINT_EXPRESSION,
                     "probe_peak": alu_probe["fp64"] / 1e12,
                     "frac_of_probe": f64 * pts / k64 / alu_probe["fp64"]}
         if f64 * pts / FP64_PEAK > bytes_launch / HBM_PEAK:
