@@ -352,6 +352,10 @@ def main(argv=None) -> int:
                 wss.append(g.new_workspace())
             meta = torch.empty(C.batch_meta_bytes(len(grids)) // 8, dtype=torch.float64,
                                device="cuda")
+            # untuned plan first (the 32x8 staged kind), then the autotuned one
+            C.batch_step(grids, states, wss, meta, 0.0, dtb, 1)
+            ku = _events_time(lambda: C.batch_step(grids, states, wss, meta, dtb, dtb, 20), 1) / 20
+            C.batch_release(meta)
             with tempfile.TemporaryDirectory() as td:
                 tpath = os.path.join(td, "tune.json")
                 C.autotune(grids, states, wss, meta, tpath)
@@ -360,9 +364,14 @@ def main(argv=None) -> int:
             C.batch_step(grids, states, wss, meta, 0.0, dtb, 1)
             kb = _events_time(lambda: C.batch_step(grids, states, wss, meta, dtb, dtb, 20), 1) / 20
             C.batch_release(meta)
-            kind = next((v["kind"] for k, v in table.items() if k.endswith("_kind")), None)
+            tk = next((v for k, v in table.items() if k.endswith("_kind")), {})
             batch[name] = {"ms_per_step": kb * 1e3, "point_steps_per_s": npts / kb,
-                           "rhs_updates_per_s": 4 * npts / kb, "kernel_kind": kind}
+                           "rhs_updates_per_s": 4 * npts / kb, "kernel_kind": tk.get("kind"),
+                           "untuned_ms_per_step": ku * 1e3,
+                           "untuned_kernel_kind": tk.get("untuned_kind"),
+                           "tuner_kinds": tk.get("kinds"),
+                           "tuner_kind0_tiles": {k.split("_")[-1]: v["tile"]
+                                                 for k, v in table.items() if "_kind0_" in k}}
             del grids, states, wss, meta
             torch.cuda.synchronize()
         batch["points"] = npts

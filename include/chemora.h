@@ -223,18 +223,42 @@ int chemora_batch_step(const chemora_patch* patches, int32_t npatches, void* met
                        double dt, int32_t nsteps, chemora_stream stream);
 int chemora_batch_release(void* meta);
 
-/* Measure tile shapes for each size class of the given patches with short
- * timed trials after a model-driven pruning (halo overhead, occupancy,
- * wave quantisation), and record the winners in an in-process table used
- * by later batch plans; when table_path is not NULL also write the table
- * there as JSON.  Runs kernels on the null stream and synchronises.
- * Patches with fd_order 6 or 8 have one kernel each: nothing is tuned,
- * CHEMORA_OK. */
+/* Choose the kernel kind and tiles of later batch plans for patches like
+ * the given ones (same precision and fd_order), recorded in an in-process
+ * table.  A performance model ranks the cached-load kind's tile candidates
+ * for each size class of patches: every tile costs its whole wavefronts
+ * (wave quantisation of ragged tiles) times a halo factor, and the kernel's
+ * static assignment of items (one share of the work list per XCD, round
+ * robin over the persistent grid) is simulated on a grid of the kernel
+ * instance's resident workgroups per CU (occupancy, from its registers and
+ * LDS) times the CUs.  The best three are timed and the fastest kept.  Then
+ * the candidate kinds of the order (4th: cached loads, staged 32x8, staged
+ * 16x16; 6th and 8th: staged 32x8, staged 16x16) are timed over the whole
+ * batch and the fastest becomes the kind of later plans (untuned: staged
+ * 32x8).  When table_path is not NULL, the model scores and timings are
+ * written there as JSON.  Runs kernels on the null stream and synchronises;
+ * destroys any plan held for meta.  Same patch validation as
+ * chemora_batch_step. */
 int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
                      const char* table_path);
 
-/* Tile shape the batch planner would use for a patch of size n (after
- * chemora_autotune, the tuned one): tile[0..2] in points. */
+/* The autotuner's performance model, for inspection and testing: predicted
+ * duration of one substage launch, in wavefront-plane units, of a batch of
+ * npatches patches with interior sizes dims[3q..3q+2] and tiles
+ * tiles[3q..3q+2] (x and y threads, planes per item) on kernel kind kind
+ * (0 cached loads; staged 1/2 4th order 32x8/16x16, 3/5 6th order, 4/6 8th
+ * order) of finite-difference order fd_order, with per_cu resident
+ * workgroups per CU and a persistent grid of grid workgroups; ghost items of
+ * ghost_width ghost zones included when ghost_width > 0.  All pointers host
+ * memory; *out receives the prediction.  INVALID on NULL or out-of-range
+ * arguments. */
+int chemora_batch_model(const int32_t* dims, const int32_t* tiles, int32_t npatches,
+                        int32_t kind, int32_t fd_order, int32_t per_cu, int32_t grid,
+                        int32_t ghost_width, double* out);
+
+/* Tile shape the batch planner would use for a 4th-order patch of size n
+ * under the current kind of that precision (the tuned one after
+ * chemora_autotune; CHEMORA_BATCH_KIND overrides): tile[0..2] in points. */
 int chemora_batch_tile(const int32_t n[3], int32_t precision, int32_t tile[3]);
 
 /* ---- two refinement levels (Sec. IV: the mesh-refinement driver) ------ */

@@ -3,7 +3,8 @@
 // tile shapes chosen by a model-driven, measured autotuner (the GPU run-time
 // library of Sec. III.B.3 auto-tunes the thread assignment with a model).
 //
-// One RK4 substage = ONE persistent kernel launch.  Its work list holds
+// One RK4 substage = ONE persistent kernel launch (batch_stage.h).  Its work
+// list holds
 //   - interior items: one (patch, tile) each -- right-hand side at the tile's
 //     points fused with the substage update (bssn_point.h), and
 //   - ghost items: a chunk of one patch's ghost points -- the analytic gauge
@@ -11,17 +12,20 @@
 //     zones of the substage's OUTPUT buffer.
 // Interior items read the input buffer and write output interiors; ghost
 // items write output ghosts only; so items never conflict and need no
-// ordering.  Workgroups take items round-robin (item = wg + r * grid), in an
-// order sorted by decreasing cost (longest-processing-time first).
+// ordering.  Workgroups take items round-robin within their XCD's share of
+// the list, in an order sorted by decreasing patch size (longest-processing-
+// time first).
 //
-// Three kernel kinds share this structure: kind 0 reads stencil neighbours
-// through the caches with a tile shape per patch (size class); kinds 1 and 2
-// stage each grid function's tile neighbourhood in LDS with async copies
-// (bssn_lds.h, ASrc, in both precisions) with 32x8 or 16x16 single-plane
-// tiles.  The autotuner picks the kind and, for kind 0,
-// the tile of each size class.  Patches with the 6th- or 8th-order operators
-// run kinds 3 and 4: 32x8 single-plane tiles staged with the wider
-// neighbourhood of those orders (HSrc), nothing to tune.
+// Kernel instances ("kinds", one translation unit each): kind 0 reads
+// stencil neighbours through the caches, with a tile of 1..4 planes per
+// patch; the staged kinds stage each grid function's tile neighbourhood in
+// LDS (bssn_lds.h: ASrc for 4th order, HSrc for the wider neighbourhood of
+// 6th and 8th order) with one single-plane tile shape each: 32x8 (kinds 1,
+// 3, 4 for orders 4, 6, 8) or 16x16 (kinds 2, 5, 6).  The autotuner
+// (chemora_autotune) picks the tile of kind 0 per size class of patches,
+// pruning the candidates with a performance model (model_time) and timing
+// the survivors, then times the candidate kinds of the batch's order over
+// the whole batch and keeps the fastest.
 //
 // The four substage launches and a one-thread clock update (t += dt) are
 // captured once into a HIP graph and replayed per step; the time lives in a
@@ -31,15 +35,14 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
-#include <cstdlib>
-#include <type_traits>
-
-#include "bssn_lds.h"
+#include "batch_kernel.h"
 
 namespace chemora {
 
@@ -52,318 +55,6 @@ const chemora_grid_desc& grid_desc(const chemora_grid* g);
 long long grid_state_elems(const chemora_grid* g);
 
 namespace {
-
-constexpr int kThreads = 256;
-// staging buffers of the LDS-staged kinds (three: two workgroups per CU fit)
-constexpr int kBatchBufs = 3;
-constexpr int kGhostChunk = 1024;  // ghost points per ghost item
-constexpr int kMaxPatches = 4096;
-
-struct PatchDesc {
-  Geo G;
-  BssnPar P;
-  Weights W;
-  long long state_off;  // byte offset of the patch's state from Batch::base
-  long long ws_off;     // same for its workspace: B1 | B2 | acc, each E doubles
-  long long E;        // elements of one state
-  long long ghosts;   // ghost points of one grid function
-  int ltx, lty, tz;   // tile: ltx * lty threads, tz planes each
-  int tiles[3];
-  int cols[2];        // column split of the xy tile grid (work-list order), 1 x 1: none
-};
-
-// Device plan buffer: patch descriptors, prefix sums of interior and ghost
-// items per patch (in work-list order), the clock.
-struct MetaLayout {
-  static long long desc_off() { return 0; }
-  static long long prefix_off(int np) { return ((long long)sizeof(PatchDesc) * np + 255) / 256 * 256; }
-  static long long gprefix_off(int np) { return prefix_off(np) + 8LL * (np + 1); }
-  static long long clock_off(int np) { return gprefix_off(np) + 8LL * (np + 1); }
-  static long long bytes(int np) { return (clock_off(np) + 8 + 255) / 256 * 256; }
-};
-
-struct Batch {
-  // Every patch pointer is base + a byte offset: derived from a kernel
-  // argument, the compiler knows it is global memory and uses global loads
-  // and stores (a pointer read from the descriptor would be generic, and
-  // its accesses FLAT instructions, which also count in the LDS wait counter
-  // and stall the LDS-staged kernels).
-  char* base;
-  const PatchDesc* pd;
-  const long long* prefix;   // interior items before patch q (work-list order)
-  const long long* gprefix;  // ghost items before patch q
-  double* clock;
-  int np;
-  long long n_interior, n_total;
-  double dt;
-  double t_out;   // stage-output time offset in units of dt (0.5, 0.5, 1, 1)
-  int stage_io;   // 1..4, or 0 (right-hand side only, into B1)
-};
-
-// Tile of a patch's l-th interior item.  A patch's items are listed column
-// by column (cols[0] x cols[1] columns of the xy tile grid), each column
-// plane by plane: cut into eight contiguous shares, one per XCD, the list
-// makes every XCD walk columns along z (as column_tile does for one block),
-// so the planes above and below the ones in flight stay in its L2.
-__host__ __device__ __forceinline__ void patch_tile(const PatchDesc& p, long long l, int& bx, int& by,
-                                           int& bz) {
-  const int cx = p.cols[0], cy = p.cols[1];
-  long long base = 0;
-  for (int c = 0; c < cx * cy; ++c) {
-    const int ux = c % cx, uy = c / cx;
-    const int xlo = ux * p.tiles[0] / cx, xhi = (ux + 1) * p.tiles[0] / cx;
-    const int ylo = uy * p.tiles[1] / cy, yhi = (uy + 1) * p.tiles[1] / cy;
-    const int wx = xhi - xlo;
-    const long long per = (long long)wx * (yhi - ylo), n = per * p.tiles[2];
-    if (l < base + n || c == cx * cy - 1) {
-      const long long r = l - base;
-      bz = (int)(r / per);
-      const int t = (int)(r - bz * per);
-      bx = xlo + t % wx;
-      by = ylo + t / wx;
-      return;
-    }
-    base += n;
-  }
-}
-
-__device__ __forceinline__ int find_patch(const long long* prefix, int np, long long item) {
-  int lo = 0, hi = np - 1;  // last q with prefix[q] <= item
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) / 2;
-    if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-// ghost point t of a patch (same enumeration as the single-grid fill)
-__device__ __forceinline__ void ghost_ijk(const Geo& G, long long t, int ijk[3]) {
-  const int g = G.g, e0 = G.n[0] + 2 * g, e1 = G.n[1] + 2 * g;
-  const long long cz = 2LL * g * e1 * e0;
-  const long long cy = (long long)G.n[2] * 2 * g * e0;
-  if (t < cz) {
-    ijk[0] = (int)(t % e0) - g;
-    const long long r = t / e0;
-    ijk[1] = (int)(r % e1) - g;
-    const int p = (int)(r / e1);
-    ijk[2] = p < g ? p - g : G.n[2] + (p - g);
-  } else if (t < cz + cy) {
-    t -= cz;
-    ijk[0] = (int)(t % e0) - g;
-    const long long r = t / e0;
-    const int p = (int)(r % (2 * g));
-    ijk[1] = p < g ? p - g : G.n[1] + (p - g);
-    ijk[2] = (int)(r / (2 * g));
-  } else {
-    t -= cz + cy;
-    const int p = (int)(t % (2 * g));
-    ijk[0] = p < g ? p - g : G.n[0] + (p - g);
-    const long long r = t / (2 * g);
-    ijk[1] = (int)(r % G.n[1]);
-    ijk[2] = (int)(r / G.n[1]);
-  }
-}
-
-// gauge wave (zero shift; exact under harmonic slicing): chi = H^-1/3,
-// gt_aa = H^2/3, gt_bb = H^-1/3, K = -(pi A/d) cos H^-3/2,
-// At_aa = -(2 pi A/3d) cos H^-5/6, At_bb = (pi A/3d) cos H^-11/6,
-// Gamt^a = -(4 pi A/3d) cos H^-5/3, alpha = sqrt(H)
-__device__ __forceinline__ void gw_store(const BssnPar& P, double xa, double t, double* f,
-                                         long long sv) {
-  const double pi = 3.141592653589793;
-  const double A = P.gw_A, d = P.gw_d;
-  const int a = P.gw_axis;
-  double s, c;
-  sincos(2.0 * pi * (xa - t) / d, &s, &c);
-  const double H = 1.0 - A * s;
-  const double L = log(H);
-  const double Hm13 = exp(-L / 3.0);
-  double v[V_N];
-#pragma unroll
-  for (int q = 0; q < V_N; ++q) v[q] = 0.0;
-  v[V_CHI] = Hm13;
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const int q = sidx(b, b);
-    if (b == a) {
-      v[V_GT + q] = exp(2.0 * L / 3.0);
-      v[V_AT + q] = -(2.0 * pi * A / (3.0 * d)) * c * exp(-5.0 * L / 6.0);
-    } else {
-      v[V_GT + q] = Hm13;
-      v[V_AT + q] = (pi * A / (3.0 * d)) * c * exp(-11.0 * L / 6.0);
-    }
-  }
-  v[V_TRK] = -(pi * A / d) * c * exp(-1.5 * L);
-  const double gam = -(4.0 * pi * A / (3.0 * d)) * c * exp(-5.0 * L / 3.0);
-#pragma unroll
-  for (int b = 0; b < 3; ++b) v[V_GAM + b] = b == a ? gam : 0.0;  // constant indices
-  v[V_ALP] = sqrt(H);
-#pragma unroll
-  for (int q = 0; q < V_N; ++q) f[q * sv] = v[q];
-}
-
-__device__ __forceinline__ double* patch_state(const Batch& B, const PatchDesc& p) {
-  return reinterpret_cast<double*>(B.base + p.state_off);
-}
-
-__device__ __forceinline__ void stage_buffers(const Batch& B, const PatchDesc& p, int io,
-                                              StageIO& s, double dt) {
-  double* const state = patch_state(B, p);
-  double* const ws = reinterpret_cast<double*>(B.base + p.ws_off);
-  double* B1 = ws;
-  double* B2 = ws + p.E;
-  double* acc = ws + 2 * p.E;
-  s.y0 = state;
-  s.acc = acc;
-  switch (io) {
-    case 0: s.yin = state; s.out = B1; s.cdt = 0.0; break;
-    case 1: s.yin = state; s.out = B1; s.cdt = 0.5 * dt; break;
-    case 2: s.yin = B1; s.out = B2; s.cdt = 0.5 * dt; break;
-    case 3: s.yin = B2; s.out = B1; s.cdt = dt; break;
-    default: s.yin = B1; s.out = state; s.cdt = dt / 6.0; break;
-  }
-}
-
-template <int KIND>
-struct KindShape {
-  static constexpr int TX = KIND == 2 ? 16 : 32, TY = KIND == 2 ? 16 : 8;
-  static constexpr int ORD = KIND == 3 ? 6 : (KIND == 4 ? 8 : 4);
-  static constexpr bool HI = KIND >= 3;
-  static constexpr int TOT = KIND == 0 ? 1
-                             : HI      ? HShape<TX, TY, ORD / 2 + 1>::TOTAL
-                                       : LdsShape<TX, TY>::TOTAL;
-  static constexpr int TOT3 = HI ? 1 : TOT;  // third buffer: the async kinds only
-  static constexpr int TAB = HI ? TOT : 1;   // offset table: the high-order kinds only
-};
-
-// kind of a plan for patches of finite-difference order ord
-inline int order_kind(int ord, int kind4) { return ord == 6 ? 3 : (ord == 8 ? 4 : kind4); }
-
-// one single-plane tile of a staged kind
-template <int STAGE, typename T, int KIND, int KOM>
-__device__ __forceinline__ void staged_tile(const PatchDesc& p, const StageIO& io, long long tile,
-                                            double* const* bufs, int* tab) {
-  constexpr int TX = KindShape<KIND>::TX, TY = KindShape<KIND>::TY;
-  const Geo& G = p.G;
-  int bx, by, k;
-  patch_tile(p, tile, bx, by, k);
-  const int tx = (int)threadIdx.x % TX, ty = (int)threadIdx.x / TX;
-  const int x0 = bx * TX, y0 = by * TY;
-  const int i = x0 + tx, j = y0 + ty;
-  T rhs[V_N];
-  if constexpr (KindShape<KIND>::HI) {
-    constexpr int ORD = KindShape<KIND>::ORD;
-    HSrc<TX, TY, ORD / 2 + 1> src;
-    src.init(G, io.yin, bufs[0], bufs[1], tab, x0, y0, k, tx, ty);
-    bssn_rhs_point<T, KO_OFF, ORD>(src, p.W, p.P, rhs);
-  } else {
-    ASrc<TX, TY, kBatchBufs> src;
-    src.init(G, io.yin, bufs, x0, y0, k, tx, ty);
-    bssn_rhs_point<T, KOM>(src, p.W, p.P, rhs);
-  }
-  if (i < G.n[0] && j < G.n[1])
-    bssn_store<STAGE, T>(io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
-                         false, p.P.enforce != 0);
-}
-
-// KOM: Kreiss-Oliger dissipation compiled in (KO_ON: patches with sigma = 0
-// add an exact zero) or out (KO_OFF: no patch dissipates)
-template <int STAGE, typename T, int KIND, int KOM>
-__global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
-  __shared__ int s_patch;
-  constexpr int TOT = KindShape<KIND>::TOT;
-  // separate arrays, one per staging buffer (see bssn_lds.h); a tiny
-  // placeholder each for kind 0
-  __shared__ double L0[TOT], L1[TOT], L2[KindShape<KIND>::TOT3];
-  __shared__ int TB[KindShape<KIND>::TAB];
-  double* bufs[3] = {L0, L1, L2};
-  __shared__ long long s_lo, s_hi;  // item range of s_patch (interior or ghost)
-  // The current patch's descriptor lives in LDS: under register pressure the
-  // compiler re-reads descriptor fields (weights, strides) inside the point
-  // code; from global memory every such read would be followed by a vmcnt
-  // wait that also drains the stencil copies in flight, from LDS it waits
-  // on lgkmcnt only.
-  __shared__ PatchDesc s_pd;
-  __shared__ int s_changed;
-  const double tnow = *B.clock;
-  // XCD x (blockIdx.x % 8) takes share x of the interior items and share x
-  // of the ghost items, in list order; its gridDim.x / 8 blocks stride it
-  const int x = (int)blockIdx.x % kNumXcd;
-  const long long R = gridDim.x / kNumXcd;
-  const long long ni = B.n_interior, ng = B.n_total - B.n_interior;
-  const long long i0 = ni * x / kNumXcd, i1 = ni * (x + 1) / kNumXcd;
-  const long long g0 = ng * x / kNumXcd, g1 = ng * (x + 1) / kNumXcd;
-  const long long share = (i1 - i0) + (g1 - g0);
-  if (threadIdx.x == 0) {
-    s_lo = 0;
-    s_hi = -1;
-  }
-  for (long long t = blockIdx.x / kNumXcd; t < share; t += R) {
-    const bool interior = t < i1 - i0;
-    const long long item = interior ? i0 + t : ni + g0 + (t - (i1 - i0));
-    __syncthreads();  // the previous item is finished by every wave
-    if (threadIdx.x == 0) {
-      s_changed = 0;
-      if (!(item >= s_lo && item < s_hi)) {
-        // consecutive items of a block mostly stay in one patch: search only
-        // when the item leaves the current patch's range
-        const int q = interior ? find_patch(B.prefix, B.np, item)
-                               : find_patch(B.gprefix, B.np, item - ni);
-        s_patch = q;
-        s_lo = interior ? B.prefix[q] : ni + B.gprefix[q];
-        s_hi = interior ? B.prefix[q + 1] : ni + B.gprefix[q + 1];
-        s_changed = 1;
-      }
-    }
-    __syncthreads();
-    if (s_changed) {  // the same value in every thread
-      static_assert(sizeof(PatchDesc) % 8 == 0, "descriptor copied in 8-byte words");
-      const unsigned long long* from =
-          reinterpret_cast<const unsigned long long*>(B.pd + s_patch);
-      unsigned long long* to = reinterpret_cast<unsigned long long*>(&s_pd);
-      for (int w = (int)threadIdx.x; w < (int)(sizeof(PatchDesc) / 8); w += kThreads)
-        to[w] = from[w];
-      __syncthreads();
-    }
-    const PatchDesc& p = s_pd;
-    const Geo& G = p.G;
-    StageIO io;
-    stage_buffers(B, p, B.stage_io, io, B.dt);
-    if (interior) {
-      const long long tile = item - B.prefix[s_patch];
-      if constexpr (KIND != 0) {
-        staged_tile<STAGE, T, KIND, KOM>(p, io, tile, bufs, TB);
-      } else {
-        int tx, ty, tzi;
-        patch_tile(p, tile, tx, ty, tzi);
-        const int lx = (int)threadIdx.x % p.ltx, ly = (int)threadIdx.x / p.ltx;
-        const int i = tx * p.ltx + lx, j = ty * p.lty + ly;
-        if (ly < p.lty && i < G.n[0] && j < G.n[1]) {
-          const int k0 = tzi * p.tz, k1 = min(k0 + p.tz, G.n[2]);
-          for (int k = k0; k < k1; ++k) {
-            const long long q = i + (long long)j * G.sy + (long long)k * G.sz;
-            T rhs[V_N];
-            GSrc src{io.yin + G.off0 + q, G.sv, G.sy, G.sz};
-            bssn_rhs_point<T, KOM>(src, p.W, p.P, rhs);
-            bssn_store<STAGE, T>(io, G, q, i, j, k, rhs, false, p.P.enforce != 0);
-          }
-        }
-      }
-    } else {
-      const long long chunk = item - B.n_interior - B.gprefix[s_patch];
-      const double t = tnow + B.t_out * B.dt;
-      for (long long gq = chunk * kGhostChunk + threadIdx.x;
-           gq < min((chunk + 1) * kGhostChunk, p.ghosts); gq += kThreads) {
-        int ijk[3];
-        ghost_ijk(G, gq, ijk);
-        const int a = p.P.gw_axis;
-        const double xa = p.P.origin[a] + ijk[a] * p.P.h[a];
-        gw_store(p.P, xa, t, io.out + G.off0 + ijk[0] + (long long)ijk[1] * G.sy +
-                                  (long long)ijk[2] * G.sz, G.sv);
-      }
-    }
-  }
-}
 
 __global__ void set_clock_kernel(double* clock, double t) { *clock = t; }
 __global__ void advance_clock_kernel(double* clock, double dt) { *clock = *clock + dt; }
@@ -388,61 +79,192 @@ __global__ void __launch_bounds__(kThreads) batch_state_ghosts_kernel(Batch B) {
   }
 }
 
-// ---- tile shapes ------------------------------------------------------------
+
+// ---- tile shapes and the performance model -------------------------------------
 
 struct Tile {
   int ltx, lty, tz;
 };
 
+// kind 0 candidates: 256 threads, 1, 2 or 4 planes per item
 const Tile kCandidates[] = {{64, 4, 1}, {64, 4, 2}, {64, 4, 4}, {32, 8, 1}, {32, 8, 2},
                             {32, 8, 4}, {16, 16, 1}, {16, 16, 2}, {16, 16, 4}};
-
 // size class of a patch for the tuning table: the x extent decides how well
 // a tile row fills a wavefront
 int size_class(const int32_t n[3]) { return n[0] <= 40 ? 0 : (n[0] <= 72 ? 1 : 2); }
 
+// staged kinds of a finite-difference order: {32x8, 16x16}
+int staged_kind(int order, bool square) {
+  if (order == 6) return square ? 5 : 3;
+  if (order == 8) return square ? 6 : 4;
+  return square ? 2 : 1;
+}
+
+Tile kind_shape(int kind) {
+  return (kind == 2 || kind == 5 || kind == 6) ? Tile{16, 16, 1} : Tile{32, 8, 1};
+}
+
 std::mutex g_table_mu;
-std::map<std::pair<int, int>, Tile> g_table;  // (precision, class) -> tuned tile (kind 0)
-std::map<int, int> g_kind;                    // precision -> tuned kernel kind
+// (precision, size class) -> tuned kind 0 tile
+std::map<std::pair<int, int>, Tile> g_table;
+// (precision, order) -> tuned kernel kind
+std::map<std::pair<int, int>, int> g_kind;
 
-// CHEMORA_BATCH_KIND=0|1|2 forces the kernel kind of new plans (ablation
-// switch, read at every plan build)
-int default_kind(int precision) {
+// Kernel kind of a new plan.  CHEMORA_BATCH_KIND (ablation switch, read at
+// every plan build): 0 = kind 0 (4th order; other orders: 32x8 staged),
+// 1 = the 32x8 staged kind of the order, 2 = its 16x16 staged kind.
+// Otherwise the tuned kind, else the 32x8 staged kind.
+int plan_kind(int precision, int order) {
   const char* e = std::getenv("CHEMORA_BATCH_KIND");
-  if (e && (e[0] == '0' || e[0] == '1' || e[0] == '2') && e[1] == 0) return e[0] - '0';
-  std::lock_guard<std::mutex> lk(g_table_mu);
-  auto it = g_kind.find(precision);
-  return it != g_kind.end() ? it->second : 1;  // untuned: staged 32x8
-}
-
-// model score (lower is better): padded-thread waste from ragged tiles, times
-// the halo re-read factor of the tile's cache footprint
-double model_cost(const Tile& t, const int32_t n[3]) {
-  const double tiles_x = std::ceil(n[0] / (double)t.ltx), tiles_y = std::ceil(n[1] / (double)t.lty);
-  const double tiles_z = std::ceil(n[2] / (double)t.tz);
-  const double work = tiles_x * t.ltx * tiles_y * t.lty * tiles_z * t.tz;
-  const double useful = (double)n[0] * n[1] * n[2];
-  const double halo = (t.ltx + 6.0) * (t.lty + 6.0) * (t.tz + 6.0) / (t.ltx * t.lty * t.tz);
-  return work / useful * (1.0 + 0.02 * halo);
-}
-
-Tile default_tile(const int32_t n[3], int precision) {
-  {
-    std::lock_guard<std::mutex> lk(g_table_mu);
-    auto it = g_table.find({precision, size_class(n)});
-    if (it != g_table.end()) return it->second;
+  if (e && (e[0] == '0' || e[0] == '1' || e[0] == '2') && e[1] == 0) {
+    if (e[0] == '0') return order == 4 ? 0 : staged_kind(order, false);
+    return staged_kind(order, e[0] == '2');
   }
+  std::lock_guard<std::mutex> lk(g_table_mu);
+  auto it = g_kind.find({precision, order});
+  return it != g_kind.end() ? it->second : staged_kind(order, false);
+}
+
+int compute_units() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
+  return cus;
+}
+
+// resident workgroups per CU of a kernel instance (its registers and LDS)
+int per_cu(int precision, int kind, bool ko) {
+  switch (kind) {
+    case 0: return batch_per_cu<0>(precision, ko);
+    case 2: return batch_per_cu<2>(precision, ko);
+    case 3: return batch_per_cu<3>(precision, ko);
+    case 4: return batch_per_cu<4>(precision, ko);
+    case 5: return batch_per_cu<5>(precision, ko);
+    case 6: return batch_per_cu<6>(precision, ko);
+    default: return batch_per_cu<1>(precision, ko);
+  }
+}
+
+// Persistent grid: as many workgroups as can be resident at once, so that
+// none waits for a slot; a multiple of 8 (one share of the list per XCD).
+int persistent_blocks(int precision, int kind, bool ko) {
+  const int b = compute_units() * per_cu(precision, kind, ko);
+  return std::max(kNumXcd, b / kNumXcd * kNumXcd);
+}
+
+// Performance model: predicted duration of one substage launch, in units of
+// one wavefront evaluating the right-hand side on one plane of its lanes.
+//  * Interior item (a tile of ltx * lty threads over tz planes):
+//    ceil(ltx * lty / 64) waves x tz planes -- a ragged tile costs its whole
+//    waves (wave quantisation) -- times a halo factor 1 + w x (points the
+//    item reads per point it computes: its stencil neighbourhood), w = 0.02
+//    for the staged kinds (every neighbourhood point is an HBM or L2 read
+//    and an LDS store) and 0.005 for kind 0 (neighbours mostly hit L1/L2),
+//    times a per-point cost of the kind: 2.6 for kind 0 (its point code,
+//    fed from the caches, measured 2.6-3.6x slower than the staged one),
+//    1 for the staged kinds.
+//  * Ghost item: its points / 64 waves x 0.25 (closed-form evaluation and
+//    stores, no stencils).
+//  * Schedule: the kernel's own static assignment -- XCD x takes share x of
+//    the interior items and of the ghost items, in list order, and its
+//    grid / 8 workgroups take every (grid / 8)-th item of the share.
+//  * Occupancy: grid = resident workgroups per CU (k) x CUs; the k
+//    workgroups of a CU share it, so a launch lasts the largest
+//    per-workgroup load x k / min(k, 2) (a 256-thread workgroup is one wave
+//    per SIMD; latency hiding saturates at two waves per SIMD).
+// halo factor times the kind's per-point cost
+double halo_factor(int kind, const Tile& t, int order) {
+  const double pts = (double)t.ltx * t.lty * t.tz;
+  const int r = order / 2 + 1;  // reach of the lopsided advection stencils
+  double reads;
+  if (kind == 0)
+    reads = (t.ltx + 2.0 * r) * (t.lty + 2.0 * r) * (t.tz + 2.0 * r);
+  else
+    reads = (t.ltx + 2.0 * r) * (t.lty + 2.0 * r) + 2.0 * (r - 1) * (t.ltx + 2.0 * r - 2) *
+            (t.lty + 2.0 * r - 2) + 2.0 * t.ltx * t.lty;
+  return kind == 0 ? 2.6 * (1.0 + 0.005 * reads / pts) : 1.0 + 0.02 * reads / pts;
+}
+
+struct ModelPatch {
+  int32_t n[3];
+  long long ghosts;
+};
+
+long long ghost_points(const Geo& G) {
+  const long long e0 = G.n[0] + 2 * G.g, e1 = G.n[1] + 2 * G.g;
+  return 2LL * G.g * e1 * e0 + (long long)G.n[2] * 2 * G.g * e0 +
+         (long long)G.n[2] * G.n[1] * 2 * G.g;
+}
+
+// work-list order of patches: decreasing size (LPT), stable
+std::vector<int> list_order(const std::vector<ModelPatch>& ps) {
+  std::vector<int> order(ps.size());
+  for (size_t q = 0; q < ps.size(); ++q) order[q] = (int)q;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (long long)ps[a].n[0] * ps[a].n[1] * ps[a].n[2] >
+           (long long)ps[b].n[0] * ps[b].n[1] * ps[b].n[2];
+  });
+  return order;
+}
+
+double model_time(const std::vector<ModelPatch>& ps, const std::vector<Tile>& tiles, int kind,
+                  int order, int k_per_cu, int grid, bool ghosts) {
+  std::vector<double> items, gitems;
+  for (int q : list_order(ps)) {
+    const Tile& t = tiles[q];
+    const long long nt = (long long)((ps[q].n[0] + t.ltx - 1) / t.ltx) *
+                         ((ps[q].n[1] + t.lty - 1) / t.lty) * ((ps[q].n[2] + t.tz - 1) / t.tz);
+    const double c = std::ceil(t.ltx * t.lty / 64.0) * t.tz * halo_factor(kind, t, order);
+    items.insert(items.end(), (size_t)nt, c);
+    if (ghosts)
+      for (long long g = 0; g < ps[q].ghosts; g += kGhostChunk)
+        gitems.push_back(0.25 * std::min<long long>(kGhostChunk, ps[q].ghosts - g) / 64.0);
+  }
+  const long long ni = (long long)items.size(), ng = (long long)gitems.size();
+  const int R = std::max(1, grid / kNumXcd);
+  double worst = 0.0;
+  std::vector<double> load(R);
+  for (int x = 0; x < kNumXcd; ++x) {
+    std::fill(load.begin(), load.end(), 0.0);
+    const long long i0 = ni * x / kNumXcd, i1 = ni * (x + 1) / kNumXcd;
+    const long long g0 = ng * x / kNumXcd, g1 = ng * (x + 1) / kNumXcd;
+    const long long share = (i1 - i0) + (g1 - g0);
+    for (long long t = 0; t < share; ++t)
+      load[t % R] += t < i1 - i0 ? items[i0 + t] : gitems[g0 + t - (i1 - i0)];
+    for (double l : load) worst = std::max(worst, l);
+  }
+  return worst * k_per_cu / std::min(k_per_cu, 2);
+}
+
+// model-best kind 0 tile of one patch with one plane per item (untuned
+// default: the most parallelism)
+Tile model_tile(const int32_t n[3]) {
   Tile best = kCandidates[0];
   double bc = 1e300;
   for (const Tile& t : kCandidates) {
-    if (t.tz != 1) continue;  // untuned default: one plane per tile, most parallelism
-    const double c = model_cost(t, n);
+    if (t.tz != 1) continue;
+    const double c = std::ceil(n[0] / (double)t.ltx) * t.ltx * std::ceil(n[1] / (double)t.lty) *
+                     t.lty * halo_factor(0, t, 4);
     if (c < bc) {
       bc = c;
       best = t;
     }
   }
   return best;
+}
+
+// tile of one patch in a plan of the given kind
+Tile kind_tile(int kind, int precision, const int32_t n[3]) {
+  if (kind != 0) return kind_shape(kind);
+  {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    auto it = g_table.find({precision, size_class(n)});
+    if (it != g_table.end()) return it->second;
+  }
+  return model_tile(n);
 }
 
 // ---- plans --------------------------------------------------------------------
@@ -472,47 +294,6 @@ void destroy_plan(Plan* p) {
   if (p->exec) hipGraphExecDestroy(p->exec);
   if (p->graph) hipGraphDestroy(p->graph);
   delete p;
-}
-
-int compute_units() {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-      cus = prop.multiProcessorCount;
-  }
-  return cus;
-}
-
-// Persistent grid: as many workgroups as can be resident at once (registers
-// and LDS of the kernel instance decide), so that none waits for a slot.
-template <typename T, int KIND, int KOM>
-int resident_blocks() {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_stage_kernel<1, T, KIND, KOM>,
-                                                   kThreads, 0) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  return compute_units() * per_cu;
-}
-
-template <typename T, int KOM>
-int persistent_blocks_t(int kind) {
-  if constexpr (KOM == KO_OFF) {  // high orders run without dissipation
-    if (kind == 3) return resident_blocks<T, 3, KOM>();
-    if (kind == 4) return resident_blocks<T, 4, KOM>();
-  }
-  switch (kind) {
-    case 1: return resident_blocks<T, 1, KOM>();
-    case 2: return resident_blocks<T, 2, KOM>();
-    default: return resident_blocks<T, 0, KOM>();
-  }
-}
-
-int persistent_blocks(int precision, int kind, bool ko) {
-  if (precision == CHEMORA_MIXED)
-    return ko ? persistent_blocks_t<float, KO_ON>(kind) : persistent_blocks_t<float, KO_OFF>(kind);
-  return ko ? persistent_blocks_t<double, KO_ON>(kind) : persistent_blocks_t<double, KO_OFF>(kind);
 }
 
 int validate_patches(const chemora_patch* patches, int32_t np, int* precision,
@@ -550,9 +331,10 @@ int validate_patches(const chemora_patch* patches, int32_t np, int* precision,
   return CHEMORA_OK;
 }
 
-// Build descriptors and the work list, upload to meta (synchronously).
+// Build descriptors and the work list with the given tile per patch, upload
+// to meta (synchronously).
 int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, double dt,
-               int precision, int kind, const Tile* forced) {
+               int precision, int kind, const std::vector<Tile>& tiles) {
   P->np = np;
   P->dt = dt;
   P->precision = precision;
@@ -562,20 +344,16 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
   P->grids.resize(np);
   P->states.resize(np);
   P->wss.resize(np);
-  P->tiles.resize(np);
+  P->tiles = tiles;
   std::vector<PatchDesc> pd(np);
-  std::vector<long long> cost(np);
+  std::vector<ModelPatch> mp(np);
   for (int q = 0; q < np; ++q) {
     const chemora_grid* g = patches[q].grid;
     P->grids[q] = g;
     P->states[q] = patches[q].state;
     P->wss[q] = patches[q].workspace;
     const Geo& G = grid_geo(g);
-    const int32_t n[3] = {G.n[0], G.n[1], G.n[2]};
-    const Tile t = (kind == 1 || kind >= 3) ? Tile{32, 8, 1}
-                   : kind == 2             ? Tile{16, 16, 1}
-                                           : (forced ? *forced : default_tile(n, precision));
-    P->tiles[q] = t;
+    const Tile t = tiles[q];
     PatchDesc& d = pd[q];
     d.G = G;
     d.P = grid_par(g);
@@ -583,9 +361,7 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     d.state_off = reinterpret_cast<char*>(patches[q].state) - reinterpret_cast<char*>(patches[0].state);
     d.ws_off = static_cast<char*>(patches[q].workspace) - reinterpret_cast<char*>(patches[0].state);
     d.E = grid_state_elems(g);
-    const long long e0 = G.n[0] + 2 * G.g, e1 = G.n[1] + 2 * G.g;
-    d.ghosts = 2LL * G.g * e1 * e0 + (long long)G.n[2] * 2 * G.g * e0 +
-               (long long)G.n[2] * G.n[1] * 2 * G.g;
+    d.ghosts = ghost_points(G);
     d.ltx = t.ltx;
     d.lty = t.lty;
     d.tz = t.tz;
@@ -601,13 +377,11 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
         d.cols[1] = c.cy;
       }
     }
-    cost[q] = (long long)G.n[0] * G.n[1] * G.n[2];
+    mp[q] = ModelPatch{{G.n[0], G.n[1], G.n[2]}, d.ghosts};
   }
-  // work-list order: patches by decreasing cost (LPT), so the biggest tiles
+  // work-list order: patches by decreasing size (LPT), so the biggest tiles
   // are handed out first and the short ones fill the tail
-  std::vector<int> order(np);
-  for (int q = 0; q < np; ++q) order[q] = q;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  const std::vector<int> order = list_order(mp);
   std::vector<PatchDesc> pds(np);
   std::vector<long long> prefix(np + 1), gprefix(np + 1);
   prefix[0] = gprefix[0] = 0;
@@ -629,8 +403,7 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     e = hipMemcpy(m + MetaLayout::gprefix_off(np), gprefix.data(), 8 * (np + 1),
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) return device_status(e, "batch plan upload");
-  // a multiple of 8 (one share of the work list per XCD)
-  P->grid_blocks = std::max(kNumXcd, persistent_blocks(precision, kind, P->ko) / kNumXcd * kNumXcd);
+  P->grid_blocks = persistent_blocks(precision, kind, P->ko);
   const double tout[5] = {0.0, 0.5, 0.5, 1.0, 1.0};
   for (int s = 0; s <= 4; ++s) {
     Batch& b = P->batch[s];
@@ -649,37 +422,28 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
   return CHEMORA_OK;
 }
 
-template <typename T, int KIND, int KOM>
-hipError_t launch_stage(const Plan* P, int s, hipStream_t st) {
-  const dim3 grid(P->grid_blocks), block(kThreads);
-  const Batch& b = P->batch[s];
-  switch (s) {
-    case 0: hipLaunchKernelGGL((batch_stage_kernel<0, T, KIND, KOM>), grid, block, 0, st, b); break;
-    case 1: hipLaunchKernelGGL((batch_stage_kernel<1, T, KIND, KOM>), grid, block, 0, st, b); break;
-    case 2: hipLaunchKernelGGL((batch_stage_kernel<2, T, KIND, KOM>), grid, block, 0, st, b); break;
-    case 3: hipLaunchKernelGGL((batch_stage_kernel<3, T, KIND, KOM>), grid, block, 0, st, b); break;
-    default: hipLaunchKernelGGL((batch_stage_kernel<4, T, KIND, KOM>), grid, block, 0, st, b); break;
+std::vector<Tile> kind_tiles(int kind, int precision, const chemora_patch* patches, int32_t np) {
+  std::vector<Tile> tiles(np);
+  for (int q = 0; q < np; ++q) {
+    const Geo& G = grid_geo(patches[q].grid);
+    const int32_t n[3] = {G.n[0], G.n[1], G.n[2]};
+    tiles[q] = kind_tile(kind, precision, n);
   }
-  return hipGetLastError();
-}
-
-template <typename T, int KOM>
-hipError_t launch_kind(const Plan* P, int s, hipStream_t st) {
-  if constexpr (KOM == KO_OFF) {
-    if (P->kind == 3) return launch_stage<T, 3, KOM>(P, s, st);
-    if (P->kind == 4) return launch_stage<T, 4, KOM>(P, s, st);
-  }
-  switch (P->kind) {
-    case 1: return launch_stage<T, 1, KOM>(P, s, st);
-    case 2: return launch_stage<T, 2, KOM>(P, s, st);
-    default: return launch_stage<T, 0, KOM>(P, s, st);
-  }
+  return tiles;
 }
 
 hipError_t launch_any(const Plan* P, int s, hipStream_t st) {
-  if (P->precision == CHEMORA_MIXED)
-    return P->ko ? launch_kind<float, KO_ON>(P, s, st) : launch_kind<float, KO_OFF>(P, s, st);
-  return P->ko ? launch_kind<double, KO_ON>(P, s, st) : launch_kind<double, KO_OFF>(P, s, st);
+  const Batch& b = P->batch[s];
+  const unsigned g = (unsigned)P->grid_blocks;
+  switch (P->kind) {
+    case 0: return launch_batch_kind<0>(P->precision, P->ko, s, b, g, st);
+    case 2: return launch_batch_kind<2>(P->precision, P->ko, s, b, g, st);
+    case 3: return launch_batch_kind<3>(P->precision, P->ko, s, b, g, st);
+    case 4: return launch_batch_kind<4>(P->precision, P->ko, s, b, g, st);
+    case 5: return launch_batch_kind<5>(P->precision, P->ko, s, b, g, st);
+    case 6: return launch_batch_kind<6>(P->precision, P->ko, s, b, g, st);
+    default: return launch_batch_kind<1>(P->precision, P->ko, s, b, g, st);
+  }
 }
 
 // capture: S1, S2, S3, S4, clock += dt
@@ -770,8 +534,9 @@ int chemora_batch_step(const chemora_patch* patches, int32_t npatches, void* met
         delete P;
         return device_status(e, "batch plan");
       }
-      st = build_plan(P, patches, npatches, meta, dt, precision,
-                      order_kind(order, default_kind(precision)), nullptr);
+      const int kind = plan_kind(precision, order);
+      st = build_plan(P, patches, npatches, meta, dt, precision, kind,
+                      kind_tiles(kind, precision, patches, npatches));
       if (st == CHEMORA_OK) st = capture_graph(P);
       if (st != CHEMORA_OK) {
         destroy_plan(P);
@@ -811,8 +576,7 @@ int chemora_batch_release(void* meta) {
 int chemora_batch_tile(const int32_t n[3], int32_t precision, int32_t tile[3]) {
   if (!n || !tile) return fail(CHEMORA_ERR_INVALID, "NULL argument");
   if (n[0] < 1 || n[1] < 1 || n[2] < 1) return fail(CHEMORA_ERR_INVALID, "n must be >= 1");
-  const int kind = default_kind(precision);
-  const Tile t = kind == 1 ? Tile{32, 8, 1} : kind == 2 ? Tile{16, 16, 1} : default_tile(n, precision);
+  const Tile t = kind_tile(plan_kind(precision, 4), precision, n);
   tile[0] = t.ltx;
   tile[1] = t.lty;
   tile[2] = t.tz;
@@ -825,7 +589,6 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
   int st = validate_patches(patches, npatches, &precision, &order);
   if (st != CHEMORA_OK) return st;
   if (!meta || !aligned(meta)) return fail(CHEMORA_ERR_INVALID, "meta must be a 256-byte aligned device pointer");
-  if (order != 4) return CHEMORA_OK;  // one kernel kind per high order: nothing to tune
   {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     // the trials rewrite meta: nothing queued may still read it
@@ -837,81 +600,108 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
       g_plans.erase(it);
     }
   }
-  // group patches by size class
-  std::map<int, std::vector<chemora_patch>> classes;
+  bool ko = false;
+  for (int q = 0; q < npatches; ++q) ko = ko || grid_par(patches[q].grid).ko_sigma != 0.0;
+  std::vector<ModelPatch> all;
   for (int q = 0; q < npatches; ++q) {
     const Geo& G = grid_geo(patches[q].grid);
-    const int32_t n[3] = {G.n[0], G.n[1], G.n[2]};
-    classes[size_class(n)].push_back(patches[q]);
+    all.push_back(ModelPatch{{G.n[0], G.n[1], G.n[2]}, ghost_points(G)});
   }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(CHEMORA_ERR_DEVICE, "event creation failed");
   std::string json = "{\n";
-  bool first = true;
-  for (auto& kv : classes) {
-    const std::vector<chemora_patch>& ps = kv.second;
-    // model-driven pruning: keep the 4 candidates with the best mean model cost
-    std::vector<std::pair<double, Tile>> scored;
-    for (const Tile& t : kCandidates) {
-      double c = 0.0;
-      for (const chemora_patch& p : ps) {
-        const Geo& G = grid_geo(p.grid);
-        const int32_t n[3] = {G.n[0], G.n[1], G.n[2]};
-        c += model_cost(t, n);
-      }
-      scored.push_back({c / ps.size(), t});
+  char buf[512];
+  // kind 0 (4th order): its tile per size class -- the model ranks the
+  // candidates over the class's patches, the best three are timed
+  if (order == 4) {
+    std::map<int, std::vector<chemora_patch>> classes;
+    std::map<int, std::vector<ModelPatch>> cmodel;
+    for (int q = 0; q < npatches; ++q) {
+      const int c = size_class(all[q].n);
+      classes[c].push_back(patches[q]);
+      cmodel[c].push_back(all[q]);
     }
-    std::stable_sort(scored.begin(), scored.end(),
-                     [](const std::pair<double, Tile>& a, const std::pair<double, Tile>& b) {
-                       return a.first < b.first;
-                     });
-    Tile best = scored[0].second;
-    float best_ms = 1e30f;
-    for (size_t c = 0; c < scored.size() && c < 4; ++c) {
-      Plan P;
-      st = build_plan(&P, ps.data(), (int)ps.size(), meta, 0.0, precision, 0, &scored[c].second);
-      float ms = 0.f;
-      if (st == CHEMORA_OK) st = time_plan(&P, e0, e1, &ms);
+    const int k = per_cu(precision, 0, ko), grid = persistent_blocks(precision, 0, ko);
+    for (auto& kv : classes) {
+      const std::vector<chemora_patch>& ps = kv.second;
+      std::vector<std::pair<double, Tile>> scored;
+      for (const Tile& t : kCandidates)
+        scored.push_back({model_time(cmodel[kv.first], std::vector<Tile>(ps.size(), t), 0, order,
+                                     k, grid, false),
+                          t});
+      std::stable_sort(scored.begin(), scored.end(),
+                       [](const std::pair<double, Tile>& a, const std::pair<double, Tile>& b) {
+                         return a.first < b.first;
+                       });
+      Tile best = scored[0].second;
+      float best_ms = 1e30f;
+      std::string trials;
+      for (size_t c = 0; c < scored.size() && c < 3; ++c) {
+        Plan P;
+        st = build_plan(&P, ps.data(), (int)ps.size(), meta, 0.0, precision, 0,
+                        std::vector<Tile>(ps.size(), scored[c].second));
+        float ms = 0.f;
+        if (st == CHEMORA_OK) st = time_plan(&P, e0, e1, &ms);
+        if (st != CHEMORA_OK) break;
+        snprintf(buf, sizeof buf,
+                 "%s{\"tile\": [%d, %d, %d], \"model\": %.1f, \"ms_per_rhs\": %.5f}", c ? ", " : "",
+                 scored[c].second.ltx, scored[c].second.lty, scored[c].second.tz, scored[c].first,
+                 ms / 3.0);
+        trials += buf;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = scored[c].second;
+        }
+      }
       if (st != CHEMORA_OK) break;
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = scored[c].second;
+      {
+        std::lock_guard<std::mutex> lk(g_table_mu);
+        g_table[{precision, kv.first}] = best;
       }
+      snprintf(buf, sizeof buf,
+               "  \"precision%d_kind0_class%d\": {\"tile\": [%d, %d, %d], \"patches\": %zu, "
+               "\"trials\": [",
+               precision, kv.first, best.ltx, best.lty, best.tz, ps.size());
+      json += buf;
+      json += trials + "]},\n";
     }
-    if (st != CHEMORA_OK) break;
-    {
-      std::lock_guard<std::mutex> lk(g_table_mu);
-      g_table[{precision, kv.first}] = best;
-    }
-    char buf[256];
-    snprintf(buf, sizeof buf,
-             "%s  \"precision%d_class%d\": {\"tile\": [%d, %d, %d], \"ms_per_rhs\": %.5f, "
-             "\"patches\": %zu}",
-             first ? "" : ",\n", precision, kv.first, best.ltx, best.lty, best.tz, best_ms / 3.0,
-             ps.size());
-    json += buf;
-    first = false;
   }
-  // kernel kind: per-patch global-load tiles (as just tuned) against the
-  // two staged kinds, each timed over the whole batch
-  float kind_ms[3] = {0.f, 0.f, 0.f};
-  int best_kind = 0;
-  for (int kind = 0; kind < 3 && st == CHEMORA_OK; ++kind) {
+  // the candidate kinds of the order over the whole batch: model prediction
+  // and measured time; the untuned default is the 32x8 staged kind
+  std::vector<int> kinds = {staged_kind(order, false), staged_kind(order, true)};
+  if (order == 4) kinds.insert(kinds.begin(), 0);
+  std::map<int, float> kind_ms;
+  std::string ks;
+  for (int kind : kinds) {
+    if (st != CHEMORA_OK) break;
+    const std::vector<Tile> tiles = kind_tiles(kind, precision, patches, npatches);
+    const double model = model_time(all, tiles, kind, order, per_cu(precision, kind, ko),
+                                    persistent_blocks(precision, kind, ko), false);
     Plan P;
-    st = build_plan(&P, patches, npatches, meta, 0.0, precision, kind, nullptr);
-    if (st == CHEMORA_OK) st = time_plan(&P, e0, e1, &kind_ms[kind]);
-    if (st == CHEMORA_OK && kind_ms[kind] < kind_ms[best_kind]) best_kind = kind;
+    st = build_plan(&P, patches, npatches, meta, 0.0, precision, kind, tiles);
+    float ms = 0.f;
+    if (st == CHEMORA_OK) st = time_plan(&P, e0, e1, &ms);
+    kind_ms[kind] = ms;
+    snprintf(buf, sizeof buf, "%s\"%d\": {\"model\": %.1f, \"per_cu\": %d, \"ms_per_rhs\": %.5f}",
+             ks.empty() ? "" : ", ", kind, model, per_cu(precision, kind, ko), ms / 3.0);
+    ks += buf;
   }
   if (st == CHEMORA_OK) {
-    std::lock_guard<std::mutex> lk(g_table_mu);
-    g_kind[precision] = best_kind;
-    char buf[256];
+    int best_kind = kinds[0];
+    for (int kind : kinds)
+      if (kind_ms[kind] < kind_ms[best_kind]) best_kind = kind;
+    {
+      std::lock_guard<std::mutex> lk(g_table_mu);
+      g_kind[{precision, order}] = best_kind;
+    }
     snprintf(buf, sizeof buf,
-             "%s  \"precision%d_kind\": {\"kind\": %d, \"ms_per_rhs\": [%.5f, %.5f, %.5f]}",
-             first ? "" : ",\n", precision, best_kind, kind_ms[0] / 3.0, kind_ms[1] / 3.0,
-             kind_ms[2] / 3.0);
+             "  \"precision%d_order%d_kind\": {\"kind\": %d, \"untuned_kind\": %d, "
+             "\"tuned_ms_per_rhs\": %.5f, \"untuned_ms_per_rhs\": %.5f, \"kinds\": {",
+             precision, order, best_kind, staged_kind(order, false), kind_ms[best_kind] / 3.0,
+             kind_ms[staged_kind(order, false)] / 3.0);
     json += buf;
+    json += ks + "}}";
   }
   json += "\n}\n";
   hipEventDestroy(e0);
@@ -923,6 +713,34 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
     fputs(json.c_str(), f);
     fclose(f);
   }
+  return CHEMORA_OK;
+}
+
+int chemora_batch_model(const int32_t* dims, const int32_t* tiles, int32_t npatches,
+                        int32_t kind, int32_t fd_order, int32_t per_cu_wg, int32_t grid,
+                        int32_t ghost_width, double* out) {
+  if (!dims || !tiles || !out) return fail(CHEMORA_ERR_INVALID, "NULL argument");
+  if (npatches < 1 || npatches > kMaxPatches)
+    return fail(CHEMORA_ERR_INVALID, "npatches must be in [1, %d]", kMaxPatches);
+  if (kind < 0 || kind >= kNumKinds) return fail(CHEMORA_ERR_INVALID, "kind must be in [0, 6]");
+  if (fd_order != 4 && fd_order != 6 && fd_order != 8)
+    return fail(CHEMORA_ERR_INVALID, "fd_order must be 4, 6 or 8");
+  if (per_cu_wg < 1 || grid < 1 || ghost_width < 0)
+    return fail(CHEMORA_ERR_INVALID, "per_cu and grid must be >= 1, ghost_width >= 0");
+  std::vector<ModelPatch> ps(npatches);
+  std::vector<Tile> ts(npatches);
+  for (int q = 0; q < npatches; ++q) {
+    for (int d = 0; d < 3; ++d)
+      if (dims[3 * q + d] < 1 || tiles[3 * q + d] < 1)
+        return fail(CHEMORA_ERR_INVALID, "patch %d: sizes and tile extents must be >= 1", q);
+    Geo G{};
+    for (int d = 0; d < 3; ++d) G.n[d] = dims[3 * q + d];
+    G.g = ghost_width;
+    ps[q] = ModelPatch{{dims[3 * q], dims[3 * q + 1], dims[3 * q + 2]},
+                       ghost_width > 0 ? ghost_points(G) : 0};
+    ts[q] = Tile{tiles[3 * q], tiles[3 * q + 1], tiles[3 * q + 2]};
+  }
+  *out = model_time(ps, ts, kind, fd_order, per_cu_wg, grid, ghost_width > 0);
   return CHEMORA_OK;
 }
 

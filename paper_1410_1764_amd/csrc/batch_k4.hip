@@ -1,0 +1,17 @@
+// batch_k4.hip -- kernel kind 4 of the batched patch path: LDS-staged 8th order, 32x8 tiles.
+#include "batch_stage.h"
+
+namespace chemora {
+
+template <>
+hipError_t launch_batch_kind<4>(int precision, bool ko, int stage, const Batch& b,
+                                  unsigned grid, hipStream_t s) {
+  return launch_stage_kind<4>(precision, ko, stage, b, grid, s);
+}
+
+template <>
+int batch_per_cu<4>(int precision, bool ko) {
+  return per_cu_kind<4>(precision, ko);
+}
+
+}  // namespace chemora

@@ -248,3 +248,29 @@ def test_probe_fma_validation():
         == C.ERR_INVALID
     assert L.chemora_probe_fma(C.FP64, ctypes.c_void_p(4096), 0, ctypes.byref(fl), None) \
         == C.ERR_INVALID
+
+
+def test_batch_model_wave_quantisation_and_schedule():
+    """The autotuner's model on cases whose answer follows from its
+    definition: a ragged tile costs its whole waves; the XCD shares and the
+    round robin over the persistent grid decide the makespan; more resident
+    workgroups per CU than two stretch it."""
+    one = C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=1, grid=8)
+    # 128 equal items, 8 XCD shares of 16, one workgroup per XCD
+    item = one / 16
+    assert C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=1, grid=128) == pytest.approx(item)
+    assert C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=1, grid=1024) == pytest.approx(item)
+    # wave quantisation: 33 points wide needs as many 32-wide tiles as 64
+    assert C.batch_model([(33, 64, 8)], [(32, 8, 1)], kind=1, grid=8) == pytest.approx(one)
+    assert C.batch_model([(32, 64, 8)], [(32, 8, 1)], kind=1, grid=8) == pytest.approx(one / 2)
+    # 9 items over 8 shares: one share holds two
+    assert C.batch_model([(32, 8, 9)], [(32, 8, 1)], kind=1, grid=8) == pytest.approx(2 * item)
+    # per-CU occupancy beyond two waves per SIMD does not speed a workgroup up
+    assert C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=1, grid=8, per_cu=4) \
+        == pytest.approx(2 * one)
+    # ghost items only add
+    assert C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=1, grid=8, ghost_width=3) > one
+    # the cached-load kind is priced above the staged kinds per point
+    assert C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=0, grid=8) > one
+    with pytest.raises(C.ChemoraError):
+        C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=7)

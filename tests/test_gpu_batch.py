@@ -91,9 +91,13 @@ def test_batch_pure_gaugewave_matches_oracle(precision, tol):
 
 @pytest.mark.parametrize("order", [6, 8])
 @pytest.mark.parametrize("precision,tol", [(C.FP64, 1e-12), (C.MIXED, 1e-5)])
-def test_batch_high_order_matches_oracle(order, precision, tol):
-    """6th- and 8th-order patches (their own staged kernel kinds) on uneven,
-    ragged patches; the autotuner has nothing to tune for them."""
+@pytest.mark.parametrize("shape", ["tuned", "2"])
+def test_batch_high_order_matches_oracle(order, precision, tol, shape, monkeypatch):
+    """6th- and 8th-order patches (their own staged kernel kinds, 32x8 and
+    16x16 tiles) on uneven, ragged patches: the kind the autotuner picks, and
+    the 16x16 kind forced."""
+    if shape != "tuned":
+        monkeypatch.setenv("CHEMORA_BATCH_KIND", shape)
     specs = SMALL[:2] + [{"n": (19, 13, 11), "h": 1 / 64, "origin": (0.7, 0.1, 0.4)}]
     grids, blocks, states, wss, y0s = _patches(specs, precision, seed=17, order=order)
     meta = torch.empty(C.batch_meta_bytes(len(grids)) // 8, dtype=torch.float64, device="cuda")
