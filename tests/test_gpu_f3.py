@@ -44,6 +44,9 @@ CASES = [
     ((8, 8, 8), 3, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0), (1, 1, 1), 3, (7, 6, 5), C.BSSN),
     # the widest ghost zones (8): 32 x 8 and 8 x 32 band tiles, fine block wider than 64
     ((48, 20, 20), 3, (0.05, 0.1, 0.1), (0.0, 0.0, 0.0), (70, 9, 5), 8, (13, 12, 14), C.WAVE),
+    # the last fine point of every axis coincides with a coarse point two short of the
+    # coarse range's end: a box's coarse window must stop at the range
+    ((16, 16, 16), 3, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0), (28, 28, 28), 3, (2, 2, 2), C.BSSN),
 ]
 
 
