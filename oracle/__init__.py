@@ -102,6 +102,9 @@ def _load():
     lib.orc_prolong.argtypes = [P, ctypes.POINTER(_DP), _DP, ctypes.c_int, ctypes.c_double, P,
                                 _DP, ctypes.c_int]
     lib.orc_prolong.restype = ctypes.c_int
+    lib.orc_rk4_prolong.argtypes = [P, ctypes.c_int, _DP, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int, P, ctypes.POINTER(_DP), _DP, ctypes.c_int]
+    lib.orc_rk4_prolong.restype = ctypes.c_int
     lib.orc_restrict.argtypes = [P, _DP, P, _DP, ctypes.c_int]
     lib.orc_restrict.restype = ctypes.c_int
     _lib = lib
@@ -260,6 +263,21 @@ def prolong(coarse: Block, yc, fine: Block, yf: np.ndarray, times=None, t=0.0) -
                            ctypes.byref(fine._p), _ptr(yf), yf.shape[0]):
         raise ValueError("oracle prolong: levels not in ratio 2, misaligned, out of reach, "
                          "or bad time levels")
+
+
+def rk4_prolong(b: Block, system: int, y: np.ndarray, t: float, dt: float, nsteps: int,
+                coarse: Block, yc, times) -> None:
+    """Advance y (a refined block) in place by nsteps RK4 steps; the ghost
+    zones of every stage (and of the result) are prolongated from the coarse
+    levels yc at ``times`` at the stage's time (see prolong)."""
+    levels = list(yc)
+    assert len(levels) == len(times) and all(a.shape[0] == y.shape[0] for a in levels)
+    arr = (_DP * len(levels))(*[_ptr(a) for a in levels])
+    tt = np.ascontiguousarray(times, dtype=np.float64)
+    if _load().orc_rk4_prolong(ctypes.byref(b._p), system, _ptr(y), float(t), float(dt),
+                               int(nsteps), ctypes.byref(coarse._p), arr, _ptr(tt), len(levels)):
+        raise ValueError("oracle rk4_prolong: a stage's prolongation failed (levels, reach or "
+                         "time levels) or allocation failed")
 
 
 def restrict(coarse: Block, yc: np.ndarray, fine: Block, yf: np.ndarray) -> None:

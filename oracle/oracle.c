@@ -762,8 +762,34 @@ static void maybe_enforce(const orc_params* p, int system, double* y) {
   if (system == ORC_BSSN && p->enforce) orc_bssn_enforce(p, y);
 }
 
-int orc_rk4(const orc_params* p, int system, int bc, double* y, double t, double dt,
-            int nsteps) {
+int orc_prolong(const orc_params* cp, const double* const* yc, const double* times, int ntimes,
+                double t, const orc_params* fp, double* yf, int nvar);
+
+/* where the ghost zones of each RK stage come from: the boundary condition
+ * bc, or (coarse != NULL) prolongation from ntimes coarse time levels at the
+ * stage time (Sec. IV: a refined block's ghosts come from the next coarser
+ * level) */
+typedef struct {
+  int bc;
+  const orc_params* coarse;
+  const double* const* yc;
+  const double* times;
+  int ntimes;
+} ghost_source;
+
+static int stage_ghosts(const orc_params* p, int system, const ghost_source* gs, double t,
+                        double* y) {
+  if (!gs->coarse) {
+    fill_ghosts(p, system, gs->bc, t, y);
+    return 0;
+  }
+  return orc_prolong(gs->coarse, gs->yc, gs->times, gs->ntimes, t, p, y, nvars_of(system));
+}
+
+/* the classical RK4 method of lines, ghosts of every stage from gs at the
+ * stage's time (t, t + dt/2, t + dt/2, t + dt, then t + dt for the result) */
+static int rk4_steps(const orc_params* p, int system, const ghost_source* gs, double* y,
+                     double t, double dt, int nsteps) {
   geom G = mkgeom(p);
   const int nvar = nvars_of(system);
   const size_t N = (size_t)nvar * G.npts;
@@ -772,25 +798,26 @@ int orc_rk4(const orc_params* p, int system, int bc, double* y, double t, double
   double* k2 = calloc(N, sizeof(double));
   double* k3 = calloc(N, sizeof(double));
   double* k4 = calloc(N, sizeof(double));
+  int fail = 0;
   if (!ys || !k1 || !k2 || !k3 || !k4) {
     free(ys); free(k1); free(k2); free(k3); free(k4);
     return 1;
   }
   memcpy(ys, y, N * sizeof(double));
-  for (int n = 0; n < nsteps; n++) {
-    fill_ghosts(p, system, bc, t, y);
+  for (int n = 0; n < nsteps && !fail; n++) {
+    fail |= stage_ghosts(p, system, gs, t, y);
     rhs(p, system, y, k1);
     axpy_interior(&G, nvar, y, 0.5 * dt, k1, ys);
     maybe_enforce(p, system, ys);
-    fill_ghosts(p, system, bc, t + 0.5 * dt, ys);
+    fail |= stage_ghosts(p, system, gs, t + 0.5 * dt, ys);
     rhs(p, system, ys, k2);
     axpy_interior(&G, nvar, y, 0.5 * dt, k2, ys);
     maybe_enforce(p, system, ys);
-    fill_ghosts(p, system, bc, t + 0.5 * dt, ys);
+    fail |= stage_ghosts(p, system, gs, t + 0.5 * dt, ys);
     rhs(p, system, ys, k3);
     axpy_interior(&G, nvar, y, dt, k3, ys);
     maybe_enforce(p, system, ys);
-    fill_ghosts(p, system, bc, t + dt, ys);
+    fail |= stage_ghosts(p, system, gs, t + dt, ys);
     rhs(p, system, ys, k4);
     for (int v = 0; v < nvar; v++) {
       const long o = v * G.npts;
@@ -805,9 +832,23 @@ int orc_rk4(const orc_params* p, int system, int bc, double* y, double t, double
     maybe_enforce(p, system, y);
     t = t + dt;
   }
-  fill_ghosts(p, system, bc, t, y);
+  if (!fail) fail |= stage_ghosts(p, system, gs, t, y);
   free(ys); free(k1); free(k2); free(k3); free(k4);
-  return 0;
+  return fail;
+}
+
+int orc_rk4(const orc_params* p, int system, int bc, double* y, double t, double dt,
+            int nsteps) {
+  const ghost_source gs = {bc, NULL, NULL, NULL, 0};
+  return rk4_steps(p, system, &gs, y, t, dt, nsteps);
+}
+
+int orc_rk4_prolong(const orc_params* p, int system, double* y, double t, double dt, int nsteps,
+                    const orc_params* coarse, const double* const* yc, const double* times,
+                    int ntimes) {
+  if (!coarse || !yc || !times) return 1;
+  const ghost_source gs = {0, coarse, yc, times, ntimes};
+  return rk4_steps(p, system, &gs, y, t, dt, nsteps);
 }
 
 /* ------------------------------------------------------------------------ */

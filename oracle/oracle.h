@@ -53,6 +53,12 @@ double orc_wave5_energy(const orc_params* p, const double* y, double* eps);
 void orc_bssn_rhs(const orc_params* p, const double* y, double* r);
 int  orc_rk4(const orc_params* p, int system, int bc, double* y, double t,
              double dt, int nsteps);
+/* RK4 steps of a refined block whose ghost zones at every stage time are
+ * prolongated (orc_prolong) from ntimes levels of the coarse block at the
+ * given times; returns 1 (state partly advanced) if a prolongation fails */
+int  orc_rk4_prolong(const orc_params* p, int system, double* y, double t, double dt,
+                     int nsteps, const orc_params* coarse, const double* const* yc,
+                     const double* times, int ntimes);
 void orc_bssn_constraints(const orc_params* p, const double* y, double* hm,
                           double norms[4]);
 void orc_stencil(const orc_params* p, const double* f, int kind, int a, int b,

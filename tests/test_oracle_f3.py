@@ -18,7 +18,12 @@ Pinned to what the mathematics fixes, not to the oracle's weight table:
   * Lagrange interpolation in time reproduces data quadratic in t from three
     coarse levels and linear data from two, and at a level's own time is
     bitwise the single-level result;
-  * levels that are not in ratio 2, misaligned, or out of reach are refused.
+  * levels that are not in ratio 2, misaligned, or out of reach are refused;
+  * RK4 on a refined block with its ghosts prolongated at every stage time
+    from three coarse levels of the exact gauge wave converges to the exact
+    solution, and its distance to the same evolution with exact ghosts falls
+    at second order (the order the stencils leave of the third-order time
+    interpolation).
 """
 import numpy as np
 import pytest
@@ -234,3 +239,64 @@ def test_prolong_in_time(orc):
         assert np.array_equal(a, b)
     with pytest.raises(ValueError):
         oracle.prolong(c, [levels[0], levels[1]], f, f.zeros(1), [0.1, 0.1], 0.0)
+
+
+def _gw_state(b, t):
+    """the gauge wave at time t on every point of block b (interior and ghosts)"""
+    from paper_1410_1764_amd import inputs as I
+    y = b.embed(I.gaugewave(b.n, b.h, b.origin, b.gw_amp, b.gw_d, b.gw_axis, t))
+    oracle.fill_gaugewave(b, y, t)
+    return y
+
+
+def _two_level_difference(N):
+    """A refined block evolved over one coarse step (two fine RK4 steps) with
+    its ghosts prolongated at every stage time from three coarse levels of
+    the exact gauge wave (harmonic slicing, zero shift: an exact solution),
+    against the same evolution with the exact gauge wave in its ghosts."""
+    hc = 1.0 / N
+    c = oracle.Block((N, 8, 8), 3, hc, (0.0, 0.0, 0.0), slicing=1, shift=0)
+    f = oracle.Block((N // 2, 4, 4), 3, hc / 2, (N // 4 * hc, 2 * hc, 2 * hc), slicing=1,
+                     shift=0)
+    dtc, t0 = 0.25 * hc, 0.1
+    times = [t0 - dtc, t0, t0 + dtc]
+    levels = [_gw_state(c, t) for t in times]
+    y0 = _gw_state(f, t0)
+    a = y0.copy()
+    oracle.rk4_prolong(f, oracle.BSSN, a, t0, dtc / 2, 2, c, levels, times)
+    b = y0.copy()
+    oracle.rk4(f, oracle.BSSN, oracle.BC_GAUGEWAVE, b, t0, dtc / 2, 2)
+    # the result's ghosts: prolongated at the end time, the third level's own
+    want = y0.copy()
+    oracle.prolong(c, levels[2], f, want)
+    m = _ghost_mask(f)
+    assert np.array_equal(a[:, m], want[:, m])
+    exact = f.interior(_gw_state(f, t0 + dtc))
+    return (float(np.abs(f.interior(a) - f.interior(b)).max()),
+            float(np.abs(f.interior(a) - exact).max()))
+
+
+def test_rk4_with_prolongated_ghosts_converges_to_the_exact_ghosts():
+    """Prolongation in space is 6th order and the quadratic in time 3rd order
+    in the coarse step; the second-derivative stencils next to the ghost
+    zones turn a ghost error of order h^3 into an interior change of order
+    dt h^3 / h^2 per step, so a refined block fed by them departs from the
+    one fed the exact solution by a difference of second order: it falls by
+    about 4 per halving of both spacings.  Against the exact solution itself
+    both converge (the exact-ghost run only at first order: its RK stages
+    are not the solution at the stage times that its ghosts hold).  A stage
+    that takes its ghosts at the wrong time leaves an error of about 3e-2
+    that does not fall; a wrong time weight, an O(1) one."""
+    (d16, e16), (d32, e32) = _two_level_difference(16), _two_level_difference(32)
+    print("prolongated vs exact ghosts:", d16, d32, d16 / d32, "vs exact solution:", e16, e32)
+    assert 0 < d32 < d16 < 2e-4
+    assert d16 / d32 > 3.5
+    assert e16 < 2e-4 and e16 / e32 > 2.5
+
+
+def test_rk4_prolong_refuses_bad_levels():
+    c, f = _levels()
+    y = f.zeros(24)
+    lv = [c.zeros(24)] * 2
+    with pytest.raises(ValueError):
+        oracle.rk4_prolong(f, oracle.BSSN, y, 0.0, 0.01, 1, c, lv, [0.0, 0.0])
