@@ -221,6 +221,35 @@ int64_t chemora_batch_meta_bytes(int32_t npatches);
  * that the caller keeps alive until chemora_batch_release(meta). */
 int chemora_batch_step(const chemora_patch* patches, int32_t npatches, void* meta, double t,
                        double dt, int32_t nsteps, chemora_stream stream);
+
+/* Coarse parent of a batch patch on a refined level (Sec. IV: the
+ * mesh-refinement driver fills a refined patch's ghost zones from the next
+ * coarser level). */
+typedef struct {
+  const chemora_grid* coarse; /* NULL: the patch keeps the analytic gauge-wave ghosts */
+  const double* levels[3];    /* ntimes coarse states (device, 256-byte aligned), read only */
+  double times[3];            /* their times, distinct */
+  int32_t ntimes;             /* 1..3 */
+} chemora_parent;
+
+/* chemora_batch_step for a batch in which some patches are refined patches
+ * of a coarser grid: parents[q] (host array of npatches entries; NULL = no
+ * parents) gives patch q's parent.  The ghost zones of such a patch -- of
+ * its state at t and of every RK stage's output, at the stage's time -- are
+ * prolongated from the parent's time levels as chemora_prolong does
+ * (degree-5 Lagrange in space, Lagrange in time through the levels),
+ * instead of the analytic gauge wave: inside the batch's persistent launch,
+ * one ghost item per box of the patch's ghost shell.  Requirements (INVALID
+ * otherwise): each parent a BSSN grid in ratio 2 to its patch whose
+ * extended block holds every coarse point the patch's ghost stencils reach
+ * (chemora_prolong's checks), time levels that overlap no state or
+ * workspace of the batch.  UNSUPPORTED: parents in batches of fd_order 6 or
+ * 8, or a patch ghost width above 5.  The plan is rebuilt (and its graph
+ * captured again) whenever a parent's grid, levels or times change, so a
+ * caller that rotates its coarse levels pays one plan per coarse step. */
+int chemora_batch_step_levels(const chemora_patch* patches, const chemora_parent* parents,
+                              int32_t npatches, void* meta, double t, double dt, int32_t nsteps,
+                              chemora_stream stream);
 int chemora_batch_release(void* meta);
 
 /* Choose the kernel kind and tiles of later batch plans for patches like

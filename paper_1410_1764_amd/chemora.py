@@ -48,6 +48,11 @@ class Patch(ctypes.Structure):
                 ("workspace", ctypes.c_void_p)]
 
 
+class Parent(ctypes.Structure):
+    _fields_ = [("coarse", ctypes.c_void_p), ("levels", ctypes.c_void_p * 3),
+                ("times", ctypes.c_double * 3), ("ntimes", ctypes.c_int32)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 
@@ -78,6 +83,8 @@ def lib():
         "chemora_batch_meta_bytes": (i64, [i32]),
         "chemora_batch_step": (ctypes.c_int, [ctypes.POINTER(Patch), i32, _vp, dbl, dbl, i32,
                                               _vp]),
+        "chemora_batch_step_levels": (ctypes.c_int, [ctypes.POINTER(Patch), ctypes.POINTER(Parent),
+                                                     i32, _vp, dbl, dbl, i32, _vp]),
         "chemora_batch_release": (ctypes.c_int, [_vp]),
         "chemora_autotune": (ctypes.c_int, [ctypes.POINTER(Patch), i32, _vp, ctypes.c_char_p]),
         "chemora_batch_tile": (ctypes.c_int, [ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]),
@@ -298,10 +305,26 @@ def _patch_array(grids, states, workspaces):
 
 
 def batch_step(grids, states, workspaces, meta, t: float, dt: float, nsteps: int = 1,
-               stream=None):
+               stream=None, parents=None):
+    """parents: None, or one entry per patch: None (analytic ghosts) or
+    (coarse Grid, [coarse level states], [times])"""
     arr = _patch_array(grids, states, workspaces)
-    check(lib().chemora_batch_step(arr, len(grids), _ptr(meta), float(t), float(dt),
-                                   int(nsteps), _stream(stream)))
+    if parents is None:
+        check(lib().chemora_batch_step(arr, len(grids), _ptr(meta), float(t), float(dt),
+                                       int(nsteps), _stream(stream)))
+        return
+    par = (Parent * len(grids))()
+    for q, pr in enumerate(parents):
+        if pr is None:
+            continue
+        coarse, levels, times = pr
+        par[q].coarse = coarse.handle.value
+        for l, (lv, tt) in enumerate(zip(levels, times)):
+            par[q].levels[l] = lv.data_ptr()
+            par[q].times[l] = float(tt)
+        par[q].ntimes = len(levels)
+    check(lib().chemora_batch_step_levels(arr, par, len(grids), _ptr(meta), float(t), float(dt),
+                                          int(nsteps), _stream(stream)))
 
 
 def batch_release(meta):

@@ -12,7 +12,7 @@
 #include <new>
 #include <string>
 
-#include "internal.h"
+#include "prolong_box.h"
 
 using namespace chemora;
 
@@ -49,6 +49,7 @@ const Geo& grid_geo(const chemora_grid* g) { return g->geo; }
 const BssnPar& grid_par(const chemora_grid* g) { return g->par; }
 const chemora_grid_desc& grid_desc(const chemora_grid* g) { return g->d; }
 long long grid_state_elems(const chemora_grid* g) { return g->state_elems; }
+int grid_nvars(const chemora_grid* g) { return g->nvars; }
 
 // constraints.hip: the static partial-sum buffer of chemora_constraints_noalloc
 long long constraints_static_capacity();
@@ -432,25 +433,30 @@ static bool overlaps(const void* a, long long an, const void* b, long long bn) {
   return x < y + bn && y < x + an;
 }
 
-int chemora_prolong(const chemora_grid* coarse, const double* const* coarse_states,
-                    const double* times, int32_t ntimes, double t, const chemora_grid* fine,
-                    double* fine_state, chemora_stream stream) {
-  int off[3];
+}  // extern "C"
+
+namespace chemora {
+
+// Shared by chemora_prolong and the batch's prolongation ghosts: the level
+// pair, the time levels (1..3 aligned states not overlapping [avoid, avoid +
+// avoid_bytes), distinct finite times) and the reach of every fine extended
+// point's stencil inside the coarse extended block.
+int check_prolong_source(const chemora_grid* coarse, const chemora_grid* fine,
+                         const double* const* levels, const double* times, int ntimes,
+                         const void* avoid, long long avoid_bytes, int off[3]) {
   int st = level_pair(coarse, fine, off);
   if (st != CHEMORA_OK) return st;
   if (ntimes < 1 || ntimes > kMaxTimeLevels)
     return fail(CHEMORA_ERR_INVALID, "ntimes must be in [1, %d], got %d", kMaxTimeLevels, ntimes);
-  if (!coarse_states || !times || !fine_state)
-    return fail(CHEMORA_ERR_INVALID, "coarse_states, times and fine_state must not be NULL");
-  if (!std::isfinite(t)) return fail(CHEMORA_ERR_INVALID, "t must be finite");
-  if (!aligned(fine_state)) return fail(CHEMORA_ERR_INVALID, "fine_state must be 256-byte aligned");
-  const long long cb = coarse->state_elems * 8, fb = fine->state_elems * 8;
+  if (!levels || !times)
+    return fail(CHEMORA_ERR_INVALID, "coarse states and times must not be NULL");
+  const long long cb = coarse->state_elems * 8;
   for (int l = 0; l < ntimes; ++l) {
-    if (!coarse_states[l] || !aligned(coarse_states[l]))
+    if (!levels[l] || !aligned(levels[l]))
       return fail(CHEMORA_ERR_INVALID, "coarse_states[%d] is NULL or not 256-byte aligned", l);
     if (!std::isfinite(times[l])) return fail(CHEMORA_ERR_INVALID, "times[%d] is not finite", l);
-    if (overlaps(coarse_states[l], cb, fine_state, fb))
-      return fail(CHEMORA_ERR_INVALID, "coarse_states[%d] overlaps fine_state", l);
+    if (avoid && overlaps(levels[l], cb, avoid, avoid_bytes))
+      return fail(CHEMORA_ERR_INVALID, "coarse_states[%d] overlaps the fine state", l);
     for (int m = 0; m < l; ++m)
       if (times[m] == times[l]) return fail(CHEMORA_ERR_INVALID, "times must be distinct");
   }
@@ -469,15 +475,27 @@ int chemora_prolong(const chemora_grid* coarse, const double* const* coarse_stat
                     "coarse extended range [%d, %d)", i, a, lo, hi, -C.g, C.n[a] + C.g);
     }
   }
-  // Lagrange weights in time at t
+  return CHEMORA_OK;
+}
+
+}  // namespace chemora
+
+extern "C" {
+
+int chemora_prolong(const chemora_grid* coarse, const double* const* coarse_states,
+                    const double* times, int32_t ntimes, double t, const chemora_grid* fine,
+                    double* fine_state, chemora_stream stream) {
+  int off[3];
+  if (!fine_state) return fail(CHEMORA_ERR_INVALID, "fine_state must not be NULL");
+  if (!std::isfinite(t)) return fail(CHEMORA_ERR_INVALID, "t must be finite");
+  if (!aligned(fine_state)) return fail(CHEMORA_ERR_INVALID, "fine_state must be 256-byte aligned");
+  int st = check_prolong_source(coarse, fine, coarse_states, times, ntimes, fine_state,
+                                fine ? fine->state_elems * 8 : 0, off);
+  if (st != CHEMORA_OK) return st;
   double wt[kMaxTimeLevels];
-  for (int l = 0; l < ntimes; ++l) {
-    wt[l] = 1.0;
-    for (int m = 0; m < ntimes; ++m)
-      if (m != l) wt[l] *= (t - times[m]) / (times[l] - times[m]);
-  }
-  return device_status(launch_prolong(C, coarse_states, wt, ntimes, F, off, coarse->nvars,
-                                      fine_state, static_cast<hipStream_t>(stream)),
+  time_weights(times, ntimes, t, wt);
+  return device_status(launch_prolong(coarse->geo, coarse_states, wt, ntimes, fine->geo, off,
+                                      coarse->nvars, fine_state, static_cast<hipStream_t>(stream)),
                        "prolongation launch");
 }
 

@@ -53,6 +53,12 @@ const Geo& grid_geo(const chemora_grid* g);
 const BssnPar& grid_par(const chemora_grid* g);
 const chemora_grid_desc& grid_desc(const chemora_grid* g);
 long long grid_state_elems(const chemora_grid* g);
+int grid_nvars(const chemora_grid* g);
+int check_prolong_source(const chemora_grid* coarse, const chemora_grid* fine,
+                         const double* const* levels, const double* times, int ntimes,
+                         const void* avoid, long long avoid_bytes, int off[3]);
+hipError_t launch_prolong(const Geo& C, const double* const* yc, const double* wt, int ntimes,
+                          const Geo& F, const int off[3], int nvar, double* yf, hipStream_t s);
 
 namespace {
 
@@ -66,6 +72,7 @@ __global__ void __launch_bounds__(kThreads) batch_state_ghosts_kernel(Batch B) {
   for (long long item = blockIdx.x; item < B.n_total - B.n_interior; item += gridDim.x) {
     const int q = find_patch(B.gprefix, B.np, item);
     const PatchDesc& p = B.pd[q];
+    if (p.parent) continue;  // prolongated on the host side of the call
     const long long chunk = item - B.gprefix[q];
     for (long long gq = chunk * kGhostChunk + threadIdx.x;
          gq < min((chunk + 1) * kGhostChunk, p.ghosts); gq += kThreads) {
@@ -136,22 +143,22 @@ int compute_units() {
 }
 
 // resident workgroups per CU of a kernel instance (its registers and LDS)
-int per_cu(int precision, int kind, bool ko) {
+int per_cu(int precision, int kind, bool ko, bool par = false) {
   switch (kind) {
-    case 0: return batch_per_cu<0>(precision, ko);
-    case 2: return batch_per_cu<2>(precision, ko);
-    case 3: return batch_per_cu<3>(precision, ko);
-    case 4: return batch_per_cu<4>(precision, ko);
-    case 5: return batch_per_cu<5>(precision, ko);
-    case 6: return batch_per_cu<6>(precision, ko);
-    default: return batch_per_cu<1>(precision, ko);
+    case 0: return batch_per_cu<0>(precision, ko, par);
+    case 2: return batch_per_cu<2>(precision, ko, par);
+    case 3: return batch_per_cu<3>(precision, ko, par);
+    case 4: return batch_per_cu<4>(precision, ko, par);
+    case 5: return batch_per_cu<5>(precision, ko, par);
+    case 6: return batch_per_cu<6>(precision, ko, par);
+    default: return batch_per_cu<1>(precision, ko, par);
   }
 }
 
 // Persistent grid: as many workgroups as can be resident at once, so that
 // none waits for a slot; a multiple of 8 (one share of the list per XCD).
-int persistent_blocks(int precision, int kind, bool ko) {
-  const int b = compute_units() * per_cu(precision, kind, ko);
+int persistent_blocks(int precision, int kind, bool ko, bool par = false) {
+  const int b = compute_units() * per_cu(precision, kind, ko, par);
   return std::max(kNumXcd, b / kNumXcd * kNumXcd);
 }
 
@@ -270,6 +277,8 @@ Tile kind_tile(int kind, int precision, const int32_t n[3]) {
 // ---- plans --------------------------------------------------------------------
 
 struct Plan {
+  std::vector<chemora_parent> parents;  // one per patch (coarse NULL: analytic ghosts)
+  std::vector<int> poff;                // 3 per patch: fine offset in its parent
   std::vector<const chemora_grid*> grids;
   std::vector<double*> states;
   std::vector<void*> wss;
@@ -278,6 +287,7 @@ struct Plan {
   int precision = 0;
   int kind = 0;
   bool ko = false;  // some patch has Kreiss-Oliger dissipation
+  bool has_parents = false;  // some patch's ghosts are prolongated from a parent
   int np = 0;
   long long n_interior = 0, n_total = 0;
   int grid_blocks = 0;
@@ -334,8 +344,18 @@ int validate_patches(const chemora_patch* patches, int32_t np, int* precision,
 // Build descriptors and the work list with the given tile per patch, upload
 // to meta (synchronously).
 int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, double dt,
-               int precision, int kind, const std::vector<Tile>& tiles) {
+               int precision, int kind, const std::vector<Tile>& tiles,
+               const chemora_parent* parents = nullptr, const int* poff = nullptr) {
   P->np = np;
+  P->parents.assign(np, chemora_parent{});
+  P->poff.assign(3 * (size_t)np, 0);
+  P->has_parents = false;
+  if (parents)
+    for (int q = 0; q < np; ++q) {
+      P->parents[q] = parents[q];
+      P->has_parents = P->has_parents || parents[q].coarse;
+      for (int d = 0; d < 3; ++d) P->poff[3 * q + d] = poff[3 * q + d];
+    }
   P->dt = dt;
   P->precision = precision;
   P->kind = kind;
@@ -377,6 +397,22 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
         d.cols[1] = c.cy;
       }
     }
+    d.parent = 0;
+    const chemora_parent& par = P->parents[q];
+    if (par.coarse) {
+      d.parent = 1;
+      d.PC = grid_geo(par.coarse);
+      for (int a = 0; a < 3; ++a) d.poff[a] = P->poff[3 * q + a];
+      d.pb = make_box_grid(G, kBatchProlongBox, kBatchProlongBox, kBatchProlongBox,
+                           kBatchProlongBox, kBatchProlongBox);
+      d.pntimes = par.ntimes;
+      for (int l = 0; l < kMaxTimeLevels; ++l) {
+        const int ll = l < par.ntimes ? l : 0;  // unused levels repeat level 0
+        d.plev[l] = reinterpret_cast<const char*>(par.levels[ll]) -
+                    reinterpret_cast<char*>(patches[0].state);
+        d.ptimes[l] = par.times[ll];
+      }
+    }
     mp[q] = ModelPatch{{G.n[0], G.n[1], G.n[2]}, d.ghosts};
   }
   // work-list order: patches by decreasing size (LPT), so the biggest tiles
@@ -389,7 +425,8 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     pds[r] = pd[order[r]];
     const PatchDesc& d = pds[r];
     prefix[r + 1] = prefix[r] + (long long)d.tiles[0] * d.tiles[1] * d.tiles[2];
-    gprefix[r + 1] = gprefix[r] + (d.ghosts + kGhostChunk - 1) / kGhostChunk;
+    gprefix[r + 1] = gprefix[r] + (d.parent ? (long long)d.pb.boxes
+                                            : (d.ghosts + kGhostChunk - 1) / kGhostChunk);
   }
   P->n_interior = prefix[np];
   P->n_total = prefix[np] + gprefix[np];
@@ -403,7 +440,7 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     e = hipMemcpy(m + MetaLayout::gprefix_off(np), gprefix.data(), 8 * (np + 1),
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) return device_status(e, "batch plan upload");
-  P->grid_blocks = persistent_blocks(precision, kind, P->ko);
+  P->grid_blocks = persistent_blocks(precision, kind, P->ko, P->has_parents);
   const double tout[5] = {0.0, 0.5, 0.5, 1.0, 1.0};
   for (int s = 0; s <= 4; ++s) {
     Batch& b = P->batch[s];
@@ -435,14 +472,15 @@ std::vector<Tile> kind_tiles(int kind, int precision, const chemora_patch* patch
 hipError_t launch_any(const Plan* P, int s, hipStream_t st) {
   const Batch& b = P->batch[s];
   const unsigned g = (unsigned)P->grid_blocks;
+  const bool par = P->has_parents;
   switch (P->kind) {
-    case 0: return launch_batch_kind<0>(P->precision, P->ko, s, b, g, st);
-    case 2: return launch_batch_kind<2>(P->precision, P->ko, s, b, g, st);
-    case 3: return launch_batch_kind<3>(P->precision, P->ko, s, b, g, st);
-    case 4: return launch_batch_kind<4>(P->precision, P->ko, s, b, g, st);
-    case 5: return launch_batch_kind<5>(P->precision, P->ko, s, b, g, st);
-    case 6: return launch_batch_kind<6>(P->precision, P->ko, s, b, g, st);
-    default: return launch_batch_kind<1>(P->precision, P->ko, s, b, g, st);
+    case 0: return launch_batch_kind<0>(P->precision, P->ko, par, s, b, g, st);
+    case 2: return launch_batch_kind<2>(P->precision, P->ko, par, s, b, g, st);
+    case 3: return launch_batch_kind<3>(P->precision, P->ko, par, s, b, g, st);
+    case 4: return launch_batch_kind<4>(P->precision, P->ko, par, s, b, g, st);
+    case 5: return launch_batch_kind<5>(P->precision, P->ko, par, s, b, g, st);
+    case 6: return launch_batch_kind<6>(P->precision, P->ko, par, s, b, g, st);
+    default: return launch_batch_kind<1>(P->precision, P->ko, par, s, b, g, st);
   }
 }
 
@@ -480,13 +518,66 @@ int time_plan(const Plan* P, hipEvent_t e0, hipEvent_t e1, float* ms) {
   return device_status(e, "autotune trial");
 }
 
-bool same_patches(const Plan* P, const chemora_patch* patches, int32_t np, double dt) {
+bool same_parent(const chemora_parent& a, const chemora_parent* b) {
+  const bool bn = !b || !b->coarse;
+  if (!a.coarse || bn) return !a.coarse && bn;
+  if (a.coarse != b->coarse || a.ntimes != b->ntimes) return false;
+  for (int l = 0; l < a.ntimes; ++l)
+    if (a.levels[l] != b->levels[l] || a.times[l] != b->times[l]) return false;
+  return true;
+}
+
+bool same_patches(const Plan* P, const chemora_patch* patches, int32_t np, double dt,
+                  const chemora_parent* parents) {
   if (P->np != np || P->dt != dt) return false;
   for (int q = 0; q < np; ++q)
     if (P->grids[q] != patches[q].grid || P->states[q] != patches[q].state ||
-        P->wss[q] != patches[q].workspace)
+        P->wss[q] != patches[q].workspace || !same_parent(P->parents[q], parents ? &parents[q] : nullptr))
       return false;
   return true;
+}
+
+// Parents of a two-level batch: each either none (coarse NULL) or a valid
+// prolongation source for its patch (chemora_prolong's checks), 4th order,
+// ghost boxes within the kernel's LDS, time levels that no patch of the
+// batch writes.  Fills off (3 per patch).
+int validate_parents(const chemora_patch* patches, const chemora_parent* parents, int32_t np,
+                     int order, int* off) {
+  for (int q = 0; q < np; ++q) {
+    for (int d = 0; d < 3; ++d) off[3 * q + d] = 0;
+    const chemora_parent& par = parents[q];
+    if (!par.coarse) continue;
+    if (order != 4)
+      return fail(CHEMORA_ERR_UNSUPPORTED,
+                  "patch %d: prolongated ghosts need fd_order 4 (the staged high-order kinds "
+                  "have no room for the prolongation boxes)", q);
+    const Geo& G = grid_geo(patches[q].grid);
+    const BoxGrid bg = make_box_grid(G, kBatchProlongBox, kBatchProlongBox, kBatchProlongBox,
+                                     kBatchProlongBox, kBatchProlongBox);
+    if (bg.lds_a > kBatchProlongLds || bg.lds_b > kBatchProlongLds || bg.boxes < 1)
+      return fail(CHEMORA_ERR_UNSUPPORTED,
+                  "patch %d: prolongated ghosts need a ghost width of at most 5, got %d", q, G.g);
+    if (grid_nvars(par.coarse) != 24)
+      return fail(CHEMORA_ERR_INVALID, "patch %d: the parent must be a BSSN grid", q);
+    const int st = check_prolong_source(par.coarse, patches[q].grid, par.levels, par.times,
+                                        par.ntimes, patches[q].state,
+                                        grid_state_elems(patches[q].grid) * 8, &off[3 * q]);
+    if (st != CHEMORA_OK) return st;
+    const long long cb = grid_state_elems(par.coarse) * 8;
+    for (int r = 0; r < np; ++r) {
+      const long long sb = grid_state_elems(patches[r].grid) * 8;
+      for (int l = 0; l < par.ntimes; ++l) {
+        const char* a = reinterpret_cast<const char*>(par.levels[l]);
+        const char* st0 = reinterpret_cast<const char*>(patches[r].state);
+        const char* w0 = static_cast<const char*>(patches[r].workspace);
+        if ((a < st0 + sb && st0 < a + cb) || (a < w0 + 3 * sb && w0 < a + cb))
+          return fail(CHEMORA_ERR_INVALID,
+                      "patch %d: parent time level %d overlaps the state or workspace of patch "
+                      "%d, which the batch writes", q, l, r);
+      }
+    }
+  }
+  return CHEMORA_OK;
 }
 
 }  // namespace
@@ -504,20 +595,29 @@ int64_t chemora_batch_meta_bytes(int32_t npatches) {
   return MetaLayout::bytes(npatches);
 }
 
-int chemora_batch_step(const chemora_patch* patches, int32_t npatches, void* meta, double t,
-                       double dt, int32_t nsteps, chemora_stream stream) {
+int chemora_batch_step_levels(const chemora_patch* patches, const chemora_parent* parents,
+                              int32_t npatches, void* meta, double t, double dt, int32_t nsteps,
+                              chemora_stream stream) {
   int precision = 0, order = 4;
   int st = validate_patches(patches, npatches, &precision, &order);
   if (st != CHEMORA_OK) return st;
   if (!meta || !aligned(meta)) return fail(CHEMORA_ERR_INVALID, "meta must be a 256-byte aligned device pointer");
   if (nsteps < 0) return fail(CHEMORA_ERR_INVALID, "nsteps must be >= 0");
   if (!std::isfinite(t) || !std::isfinite(dt)) return fail(CHEMORA_ERR_INVALID, "t and dt must be finite");
+  std::vector<int> off(3 * (size_t)npatches, 0);
+  bool any_parent = false;
+  if (parents) {
+    st = validate_parents(patches, parents, npatches, order, off.data());
+    if (st != CHEMORA_OK) return st;
+    for (int q = 0; q < npatches; ++q) any_parent = any_parent || parents[q].coarse;
+  }
+  const chemora_parent* par = any_parent ? parents : nullptr;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Plan* P = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     auto it = g_plans.find(meta);
-    if (it != g_plans.end() && same_patches(it->second, patches, npatches, dt) &&
+    if (it != g_plans.end() && same_patches(it->second, patches, npatches, dt, par) &&
         it->second->precision == precision) {
       P = it->second;
     } else {
@@ -536,7 +636,7 @@ int chemora_batch_step(const chemora_patch* patches, int32_t npatches, void* met
       }
       const int kind = plan_kind(precision, order);
       st = build_plan(P, patches, npatches, meta, dt, precision, kind,
-                      kind_tiles(kind, precision, patches, npatches));
+                      kind_tiles(kind, precision, patches, npatches), par, off.data());
       if (st == CHEMORA_OK) st = capture_graph(P);
       if (st != CHEMORA_OK) {
         destroy_plan(P);
@@ -556,11 +656,28 @@ int chemora_batch_step(const chemora_patch* patches, int32_t npatches, void* met
     st = device_status(hipGetLastError(), "batch ghost fill");
     if (st != CHEMORA_OK) return st;
   }
+  // the states' ghosts of the patches with a parent: prolongated at t
+  for (int q = 0; q < npatches && par; ++q) {
+    const chemora_parent& pr = par[q];
+    if (!pr.coarse) continue;
+    double wt[kMaxTimeLevels];
+    time_weights(pr.times, pr.ntimes, t, wt);
+    st = device_status(launch_prolong(grid_geo(pr.coarse), pr.levels, wt, pr.ntimes,
+                                      grid_geo(patches[q].grid), &off[3 * q], 24,
+                                      patches[q].state, s),
+                       "batch parent prolongation");
+    if (st != CHEMORA_OK) return st;
+  }
   for (int n = 0; n < nsteps; ++n) {
     st = device_status(hipGraphLaunch(P->exec, s), "batch graph launch");
     if (st != CHEMORA_OK) return st;
   }
   return CHEMORA_OK;
+}
+
+int chemora_batch_step(const chemora_patch* patches, int32_t npatches, void* meta, double t,
+                       double dt, int32_t nsteps, chemora_stream stream) {
+  return chemora_batch_step_levels(patches, nullptr, npatches, meta, t, dt, nsteps, stream);
 }
 
 int chemora_batch_release(void* meta) {

@@ -5,14 +5,14 @@
 namespace chemora {
 
 template <>
-hipError_t launch_batch_kind<0>(int precision, bool ko, int stage, const Batch& b,
+hipError_t launch_batch_kind<0>(int precision, bool ko, bool par, int stage, const Batch& b,
                                   unsigned grid, hipStream_t s) {
-  return launch_stage_kind<0>(precision, ko, stage, b, grid, s);
+  return launch_stage_kind<0>(precision, ko, par, stage, b, grid, s);
 }
 
 template <>
-int batch_per_cu<0>(int precision, bool ko) {
-  return per_cu_kind<0>(precision, ko);
+int batch_per_cu<0>(int precision, bool ko, bool par) {
+  return per_cu_kind<0>(precision, ko, par);
 }
 
 }  // namespace chemora

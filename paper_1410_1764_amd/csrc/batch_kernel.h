@@ -5,6 +5,7 @@
 #pragma once
 
 #include "bssn_lds.h"
+#include "prolong_box.h"
 
 namespace chemora {
 
@@ -25,7 +26,24 @@ struct PatchDesc {
   int ltx, lty, tz;   // tile: ltx * lty threads, tz planes each
   int tiles[3];
   int cols[2];        // column split of the xy tile grid (work-list order), 1 x 1: none
+  // Ghosts prolongated from a coarse parent (parent != 0) instead of the
+  // analytic gauge wave: the parent's geometry, the fine offset, the boxes
+  // of the ghost shell (one ghost item each, all grid functions), the byte
+  // offsets of the parent's time levels from Batch::base and their times.
+  int parent;
+  int poff[3];
+  int pntimes;
+  Geo PC;
+  BoxGrid pb;
+  long long plev[kMaxTimeLevels];
+  double ptimes[kMaxTimeLevels];
 };
+
+// Prolongation ghost boxes of the batch: 16 x 16 slab columns, 16-point band
+// boxes 16 planes deep; both LDS buffers within kBatchProlongLds doubles for
+// ghost widths up to 5 (checked on the host per patch).
+constexpr int kBatchProlongBox = 16;
+constexpr int kBatchProlongLds = 2048;
 
 // Device plan buffer: patch descriptors, prefix sums of interior and ghost
 // items per patch (in work-list order), the clock.
@@ -186,20 +204,21 @@ __device__ __forceinline__ void stage_buffers(const Batch& B, const PatchDesc& p
 //   kinds 3 / 5: LDS-staged 6th order, 32x8 / 16x16
 //   kinds 4 / 6: LDS-staged 8th order, 32x8 / 16x16
 // launch_batch_kind<K>: one substage (0 = right-hand side only, 1..4) over
-// the work list of b on grid workgroups; batch_per_cu<K>: resident
-// workgroups per CU of that instance (its registers and LDS decide).
+// the work list of b on grid workgroups, the instance with prolongation
+// ghost items when par; batch_per_cu<K>: resident workgroups per CU of that
+// instance (its registers and LDS decide).
 constexpr int kNumKinds = 7;
 template <int K>
-hipError_t launch_batch_kind(int precision, bool ko, int stage, const Batch& b, unsigned grid,
-                             hipStream_t s);
+hipError_t launch_batch_kind(int precision, bool ko, bool par, int stage, const Batch& b,
+                             unsigned grid, hipStream_t s);
 template <int K>
-int batch_per_cu(int precision, bool ko);
+int batch_per_cu(int precision, bool ko, bool par);
 #define CHEMORA_BATCH_KIND_DECL(K)                                                            \
   template <>                                                                                 \
-  hipError_t launch_batch_kind<K>(int precision, bool ko, int stage, const Batch& b,          \
+  hipError_t launch_batch_kind<K>(int precision, bool ko, bool par, int stage, const Batch& b, \
                                   unsigned grid, hipStream_t s);                              \
   template <>                                                                                 \
-  int batch_per_cu<K>(int precision, bool ko);
+  int batch_per_cu<K>(int precision, bool ko, bool par);
 CHEMORA_BATCH_KIND_DECL(0)
 CHEMORA_BATCH_KIND_DECL(1)
 CHEMORA_BATCH_KIND_DECL(2)

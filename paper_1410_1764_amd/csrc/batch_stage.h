@@ -25,12 +25,36 @@ struct KindShape {
   static constexpr int TX = WIDE ? 32 : 16, TY = WIDE ? 8 : 16;
   static constexpr int ORD = (KIND == 3 || KIND == 5) ? 6 : ((KIND == 4 || KIND == 6) ? 8 : 4);
   static constexpr bool HI = ORD != 4;
-  static constexpr int TOT = KIND == 0 ? 1
+  // kind 0: its first two buffers hold the prolongation ghost boxes only
+  static constexpr int TOT = KIND == 0 ? kBatchProlongLds
                              : HI      ? HShape<TX, TY, ORD / 2 + 1>::TOTAL
                                        : LdsShape<TX, TY>::TOTAL;
-  static constexpr int TOT3 = HI ? 1 : TOT;  // third buffer: the async kinds only
+  static constexpr int TOT3 = (HI || KIND == 0) ? 1 : TOT;  // third buffer: async kinds only
   static constexpr int TAB = HI ? TOT : 1;   // offset table: the high-order kinds only
 };
+
+// A prolongation ghost item: box `box` of the patch's ghost shell, every
+// grid function, prolongated from the parent's time levels at time t into
+// out (the stage's output).  A and Bb: two LDS buffers of kBatchProlongLds.
+// Compiled only into the stage kernel's PAR instances: its code raises the
+// register pressure of the whole kernel (FP64 spills of 20-36 B per lane)
+// although it never runs beside the point code.
+__device__ __forceinline__ void prolong_ghost_item(const Batch& B, const PatchDesc& p, int box,
+                                                   double t, double* out, double* A,
+                                                   double* Bb) {
+  Box x;
+  box_geometry(p.pb, p.PC, p.G, p.poff, box, x);
+  double wt[kMaxTimeLevels] = {0.0, 0.0, 0.0};
+  time_weights(p.ptimes, p.pntimes, t, wt);
+  for (int v = 0; v < V_N; ++v) {
+    const double* lev[kMaxTimeLevels];
+#pragma unroll
+    for (int l = 0; l < kMaxTimeLevels; ++l)
+      lev[l] = reinterpret_cast<const double*>(B.base + p.plev[l]) + (long long)v * p.PC.sv;
+    prolong_box(x, p.PC, p.G, lev, wt, p.pntimes, out + p.G.off0 + (long long)v * p.G.sv, A, Bb);
+    __syncthreads();  // A and Bb are reused by the next grid function
+  }
+}
 
 // one single-plane tile of a staged kind
 template <int STAGE, typename T, int KIND, int KOM>
@@ -61,7 +85,9 @@ __device__ __forceinline__ void staged_tile(const PatchDesc& p, const StageIO& i
 
 // KOM: Kreiss-Oliger dissipation compiled in (KO_ON: patches with sigma = 0
 // add an exact zero) or out (KO_OFF: no patch dissipates)
-template <int STAGE, typename T, int KIND, int KOM>
+// PAR: some patch of the batch has a coarse parent (prolongation ghost
+// items compiled in; 4th-order kinds only)
+template <int STAGE, typename T, int KIND, int KOM, bool PAR>
 __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
   __shared__ int s_patch;
   constexpr int TOT = KindShape<KIND>::TOT;
@@ -145,6 +171,13 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
     } else {
       const long long chunk = item - B.n_interior - B.gprefix[s_patch];
       const double t = tnow + B.t_out * B.dt;
+      if constexpr (PAR && !KindShape<KIND>::HI) {
+        static_assert(KindShape<KIND>::TOT >= kBatchProlongLds, "LDS for prolongation boxes");
+        if (p.parent) {  // the same value in every thread
+          prolong_ghost_item(B, p, (int)chunk, t, io.out, L0, L1);
+          continue;
+        }
+      }
       for (long long gq = chunk * kGhostChunk + threadIdx.x;
            gq < min((chunk + 1) * kGhostChunk, p.ghosts); gq += kThreads) {
         int ijk[3];
@@ -158,50 +191,67 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
   }
 }
 
-template <typename T, int KIND, int KOM>
+template <typename T, int KIND, int KOM, bool PAR>
 hipError_t launch_stage_t(int stage, const Batch& b, unsigned grid, hipStream_t st) {
   const dim3 g(grid), blk(kThreads);
   switch (stage) {
-    case 0: hipLaunchKernelGGL((batch_stage_kernel<0, T, KIND, KOM>), g, blk, 0, st, b); break;
-    case 1: hipLaunchKernelGGL((batch_stage_kernel<1, T, KIND, KOM>), g, blk, 0, st, b); break;
-    case 2: hipLaunchKernelGGL((batch_stage_kernel<2, T, KIND, KOM>), g, blk, 0, st, b); break;
-    case 3: hipLaunchKernelGGL((batch_stage_kernel<3, T, KIND, KOM>), g, blk, 0, st, b); break;
-    default: hipLaunchKernelGGL((batch_stage_kernel<4, T, KIND, KOM>), g, blk, 0, st, b); break;
+    case 0: hipLaunchKernelGGL((batch_stage_kernel<0, T, KIND, KOM, PAR>), g, blk, 0, st, b); break;
+    case 1: hipLaunchKernelGGL((batch_stage_kernel<1, T, KIND, KOM, PAR>), g, blk, 0, st, b); break;
+    case 2: hipLaunchKernelGGL((batch_stage_kernel<2, T, KIND, KOM, PAR>), g, blk, 0, st, b); break;
+    case 3: hipLaunchKernelGGL((batch_stage_kernel<3, T, KIND, KOM, PAR>), g, blk, 0, st, b); break;
+    default: hipLaunchKernelGGL((batch_stage_kernel<4, T, KIND, KOM, PAR>), g, blk, 0, st, b); break;
   }
   return hipGetLastError();
 }
 
-// KO_ON instances exist for the 4th-order kinds only (the high orders run
-// without dissipation)
-template <int KIND>
-hipError_t launch_stage_kind(int precision, bool ko, int stage, const Batch& b, unsigned grid,
-                             hipStream_t st) {
+template <typename T, int KIND, int KOM>
+hipError_t launch_stage_p(bool par, int stage, const Batch& b, unsigned grid, hipStream_t st) {
   if constexpr (!KindShape<KIND>::HI) {
-    if (ko)
-      return precision == CHEMORA_MIXED ? launch_stage_t<float, KIND, KO_ON>(stage, b, grid, st)
-                                        : launch_stage_t<double, KIND, KO_ON>(stage, b, grid, st);
+    if (par) return launch_stage_t<T, KIND, KOM, true>(stage, b, grid, st);
   }
-  return precision == CHEMORA_MIXED ? launch_stage_t<float, KIND, KO_OFF>(stage, b, grid, st)
-                                    : launch_stage_t<double, KIND, KO_OFF>(stage, b, grid, st);
+  return launch_stage_t<T, KIND, KOM, false>(stage, b, grid, st);
 }
 
-template <typename T, int KIND, int KOM>
+// KO_ON and PAR instances exist for the 4th-order kinds only (the high
+// orders run without dissipation and without parents)
+template <int KIND>
+hipError_t launch_stage_kind(int precision, bool ko, bool par, int stage, const Batch& b,
+                             unsigned grid, hipStream_t st) {
+  if constexpr (!KindShape<KIND>::HI) {
+    if (ko)
+      return precision == CHEMORA_MIXED
+                 ? launch_stage_p<float, KIND, KO_ON>(par, stage, b, grid, st)
+                 : launch_stage_p<double, KIND, KO_ON>(par, stage, b, grid, st);
+  }
+  return precision == CHEMORA_MIXED ? launch_stage_p<float, KIND, KO_OFF>(par, stage, b, grid, st)
+                                    : launch_stage_p<double, KIND, KO_OFF>(par, stage, b, grid, st);
+}
+
+template <typename T, int KIND, int KOM, bool PAR>
 int per_cu_t() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_stage_kernel<1, T, KIND, KOM>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_stage_kernel<1, T, KIND, KOM, PAR>,
                                                    kThreads, 0) != hipSuccess || n < 1)
     n = 1;
   return n;
 }
 
-template <int KIND>
-int per_cu_kind(int precision, bool ko) {
+template <typename T, int KIND, int KOM>
+int per_cu_p(bool par) {
   if constexpr (!KindShape<KIND>::HI) {
-    if (ko) return precision == CHEMORA_MIXED ? per_cu_t<float, KIND, KO_ON>()
-                                              : per_cu_t<double, KIND, KO_ON>();
+    if (par) return per_cu_t<T, KIND, KOM, true>();
   }
-  return precision == CHEMORA_MIXED ? per_cu_t<float, KIND, KO_OFF>()
-                                    : per_cu_t<double, KIND, KO_OFF>();
+  return per_cu_t<T, KIND, KOM, false>();
+}
+
+template <int KIND>
+int per_cu_kind(int precision, bool ko, bool par) {
+  if constexpr (!KindShape<KIND>::HI) {
+    if (ko) return precision == CHEMORA_MIXED ? per_cu_p<float, KIND, KO_ON>(par)
+                                              : per_cu_p<double, KIND, KO_ON>(par);
+  }
+  return precision == CHEMORA_MIXED ? per_cu_p<float, KIND, KO_OFF>(par)
+                                    : per_cu_p<double, KIND, KO_OFF>(par);
 }
 
 }  // namespace
