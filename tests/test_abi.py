@@ -274,3 +274,57 @@ def test_batch_model_wave_quantisation_and_schedule():
     assert C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=0, grid=8) > one
     with pytest.raises(C.ChemoraError):
         C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=7)
+
+
+def test_batch_parent_validation_without_a_device():
+    """chemora_batch_step_levels refuses bad parents before touching the
+    device: ratio and reach (INVALID), a time level inside a patch's state
+    (INVALID), parents for high-order batches or wide ghost zones
+    (UNSUPPORTED)."""
+    L = C.lib()
+    fine = C.Grid((16, 16, 16), 3, 1 / 64, origin=(4 / 64, 4 / 64, 4 / 64), system=C.BSSN,
+                  boundary=C.BC_GAUGEWAVE, slicing=C.SLICING_HARMONIC, shift=C.SHIFT_FROZEN)
+    coarse = C.Grid((24, 24, 24), 3, 1 / 32, system=C.BSSN, boundary=C.BC_CALLER)
+    arr = (C.Patch * 1)()
+    arr[0].grid = fine.handle.value
+    arr[0].state = 1 << 32
+    arr[0].workspace = 1 << 33
+    meta = ctypes.c_void_p(1 << 30)
+    par = (C.Parent * 1)()
+
+    def step():
+        return L.chemora_batch_step_levels(arr, par, 1, meta, 0.0, 0.001, 1, None)
+
+    def parent(grid, levels, times):
+        par[0].coarse = grid.handle.value
+        for l, (lv, t) in enumerate(zip(levels, times)):
+            par[0].levels[l] = lv
+            par[0].times[l] = t
+        par[0].ntimes = len(levels)
+
+    lv = [1 << 36, (1 << 36) + (1 << 31), (1 << 36) + (1 << 32)]
+    # spacing not in ratio 2
+    parent(C.Grid((24, 24, 24), 3, 1 / 48, system=C.BSSN, boundary=C.BC_CALLER), lv,
+           [0.0, 0.5, 1.0])
+    assert step() == C.ERR_INVALID and "twice" in C.last_error()
+    # a coarse block too small for the fine ghosts' stencils
+    parent(C.Grid((8, 8, 8), 3, 1 / 32, system=C.BSSN, boundary=C.BC_CALLER), lv,
+           [0.0, 0.5, 1.0])
+    assert step() == C.ERR_INVALID and "outside the coarse extended range" in C.last_error()
+    # a time level inside the patch's own state
+    parent(coarse, [lv[0], arr[0].state, lv[2]], [0.0, 0.5, 1.0])
+    assert step() == C.ERR_INVALID and "overlaps" in C.last_error()
+    parent(coarse, lv, [0.0, 0.5, 0.5])
+    assert step() == C.ERR_INVALID and "distinct" in C.last_error()
+    # ghost zones wider than the batch's prolongation boxes allow
+    wide = C.Grid((16, 16, 16), 6, 1 / 64, origin=(8 / 64, 8 / 64, 8 / 64), system=C.BSSN,
+                  boundary=C.BC_GAUGEWAVE, slicing=C.SLICING_HARMONIC, shift=C.SHIFT_FROZEN)
+    arr[0].grid = wide.handle.value
+    parent(coarse, lv, [0.0, 0.5, 1.0])
+    assert step() == C.ERR_UNSUPPORTED and "ghost width" in C.last_error()
+    # parents in a 6th-order batch
+    g6 = C.Grid((16, 16, 16), 4, 1 / 64, origin=(8 / 64, 8 / 64, 8 / 64), system=C.BSSN,
+                boundary=C.BC_GAUGEWAVE, slicing=C.SLICING_HARMONIC, shift=C.SHIFT_FROZEN,
+                fd_order=6, precision=C.MIXED)
+    arr[0].grid = g6.handle.value
+    assert step() == C.ERR_UNSUPPORTED and "fd_order 4" in C.last_error()
