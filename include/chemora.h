@@ -211,10 +211,12 @@ int64_t chemora_batch_meta_bytes(int32_t npatches);
 /* Advance every patch by nsteps RK4 steps of size dt from time t.  All
  * patches must share one system (BSSN), one precision, one fd_order and the
  * gauge-wave boundary (INVALID otherwise); FP64 batches of fd_order 6 return
- * CHEMORA_ERR_UNSUPPORTED (mixed precision and fd_order 8 run).  Each RK substage is ONE persistent kernel launch over a work
- * list of (patch, tile) items plus the analytic ghost zones of the next
- * stage; the four substages and the clock update are captured once in a
- * HIP graph that is replayed once per step.  The plan (tile shape per
+ * CHEMORA_ERR_UNSUPPORTED (mixed precision and fd_order 8 run).  Each RK
+ * substage is ONE kernel launch over a work list of (patch, tile) items
+ * plus the analytic ghost zones of the next stage (FP64 4th order: a
+ * resident grid that strides the list; otherwise one workgroup per item);
+ * the four substages and the clock update are captured once in a HIP graph
+ * that is replayed once per step.  The plan (tile shape per
  * patch, work list, graph) is built on the first call for a given meta
  * buffer and patch list, and reused while the same meta pointer, patch list
  * and dt are passed; meta: chemora_batch_meta_bytes(npatches) device bytes
@@ -238,7 +240,7 @@ typedef struct {
  * its state at t and of every RK stage's output, at the stage's time -- are
  * prolongated from the parent's time levels as chemora_prolong does
  * (degree-5 Lagrange in space, Lagrange in time through the levels),
- * instead of the analytic gauge wave: inside the batch's persistent launch,
+ * instead of the analytic gauge wave: inside the batch's substage launch,
  * one ghost item per box of the patch's ghost shell.  Requirements (INVALID
  * otherwise): each parent a BSSN grid in ratio 2 to its patch whose
  * extended block holds every coarse point the patch's ghost stencils reach
@@ -258,7 +260,8 @@ int chemora_batch_release(void* meta);
  * for each size class of patches: every tile costs its whole wavefronts
  * (wave quantisation of ragged tiles) times a halo factor, and the kernel's
  * static assignment of items (one share of the work list per XCD, round
- * robin over the persistent grid) is simulated on a grid of the kernel
+ * robin over a persistent grid, or greedy hand-out of one item per
+ * workgroup, as the instance runs) is simulated on a grid of the kernel
  * instance's resident workgroups per CU (occupancy, from its registers and
  * LDS) times the CUs.  The best three are timed and the fastest kept.  Then
  * the candidate kinds of the order (4th: cached loads, staged 32x8, staged
@@ -276,14 +279,16 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
  * npatches patches with interior sizes dims[3q..3q+2] and tiles
  * tiles[3q..3q+2] (x and y threads, planes per item) on kernel kind kind
  * (0 cached loads; staged 1/2 4th order 32x8/16x16, 3/5 6th order, 4/6 8th
- * order) of finite-difference order fd_order, with per_cu resident
- * workgroups per CU and a persistent grid of grid workgroups; ghost items of
- * ghost_width ghost zones included when ghost_width > 0.  All pointers host
- * memory; *out receives the prediction.  INVALID on NULL or out-of-range
- * arguments. */
+ * order; 7 4th order z-blocked 32x8x2) of finite-difference order fd_order,
+ * with per_cu resident workgroups per CU and grid of them resident in all;
+ * ghost items of ghost_width ghost zones included when ghost_width > 0;
+ * per_item != 0: one item per workgroup, handed out by the hardware
+ * (greedy), else a persistent grid striding each XCD's share (static).
+ * All pointers host memory; *out receives the prediction.  INVALID on NULL
+ * or out-of-range arguments. */
 int chemora_batch_model(const int32_t* dims, const int32_t* tiles, int32_t npatches,
                         int32_t kind, int32_t fd_order, int32_t per_cu, int32_t grid,
-                        int32_t ghost_width, double* out);
+                        int32_t ghost_width, int32_t per_item, double* out);
 
 /* Tile shape the batch planner would use for a 4th-order patch of size n
  * under the current kind of that precision (the tuned one after

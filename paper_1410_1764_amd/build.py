@@ -14,7 +14,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libchemora.so")
 SOURCES = ["api.cpp", "ghost.hip", "wave.hip", "wave5.hip", "bssn.hip", "bssn_split.hip",
            "constraints.hip", "batch.hip", "batch_k0.hip", "batch_k1.hip", "batch_k2.hip",
-           "batch_k3.hip", "batch_k4.hip", "batch_k5.hip", "batch_k6.hip", "amr.hip", "probe.hip"]
+           "batch_k3.hip", "batch_k4.hip", "batch_k5.hip", "batch_k6.hip", "batch_k7.hip", "amr.hip",
+           "probe.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled: hipcc only emits ordinary FP32 ops

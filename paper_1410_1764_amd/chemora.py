@@ -89,7 +89,7 @@ def lib():
         "chemora_autotune": (ctypes.c_int, [ctypes.POINTER(Patch), i32, _vp, ctypes.c_char_p]),
         "chemora_batch_tile": (ctypes.c_int, [ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]),
         "chemora_batch_model": (ctypes.c_int, [ctypes.POINTER(i32), ctypes.POINTER(i32), i32, i32,
-                                               i32, i32, i32, i32, ctypes.POINTER(dbl)]),
+                                               i32, i32, i32, i32, i32, ctypes.POINTER(dbl)]),
         "chemora_probe_copy": (ctypes.c_int, [_vp, _vp, i64, _vp]),
         "chemora_probe_fma_bytes": (i64, []),
         "chemora_probe_fma": (ctypes.c_int, [i32, _vp, i32, ctypes.POINTER(dbl), _vp]),
@@ -338,14 +338,14 @@ def autotune(grids, states, workspaces, meta, table_path: str | None = None):
 
 
 def batch_model(dims, tiles, kind: int, fd_order: int = 4, per_cu: int = 1, grid: int = 256,
-                ghost_width: int = 0) -> float:
+                ghost_width: int = 0, per_item: bool = False) -> float:
     """the autotuner's model: predicted launch duration (wavefront-plane units)"""
     np_ = len(dims)
     d = (ctypes.c_int32 * (3 * np_))(*[int(v) for n in dims for v in n])
     t = (ctypes.c_int32 * (3 * np_))(*[int(v) for tl in tiles for v in tl])
     out = ctypes.c_double()
     check(lib().chemora_batch_model(d, t, np_, int(kind), int(fd_order), int(per_cu), int(grid),
-                                    int(ghost_width), ctypes.byref(out)))
+                                    int(ghost_width), int(bool(per_item)), ctypes.byref(out)))
     return out.value
 
 

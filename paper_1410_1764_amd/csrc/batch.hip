@@ -3,7 +3,7 @@
 // tile shapes chosen by a model-driven, measured autotuner (the GPU run-time
 // library of Sec. III.B.3 auto-tunes the thread assignment with a model).
 //
-// One RK4 substage = ONE persistent kernel launch (batch_stage.h).  Its work
+// One RK4 substage = ONE kernel launch (batch_stage.h).  Its work
 // list holds
 //   - interior items: one (patch, tile) each -- right-hand side at the tile's
 //     points fused with the substage update (bssn_point.h), and
@@ -12,16 +12,22 @@
 //     zones of the substage's OUTPUT buffer.
 // Interior items read the input buffer and write output interiors; ghost
 // items write output ghosts only; so items never conflict and need no
-// ordering.  Workgroups take items round-robin within their XCD's share of
-// the list, in an order sorted by decreasing patch size (longest-processing-
-// time first).
+// ordering.  The list is sorted by decreasing patch size (longest-
+// processing-time first) and cut into one share per XCD.  FP64 4th-order
+// instances run a resident grid whose workgroups stride their XCD's share;
+// every other instance gets one workgroup per item and the hardware hands
+// them out in order (a loop of one iteration, so the compiler does not hold
+// loop-invariant values through the point code: that cost mixed batches a
+// wave per SIMD and spilled the high-order instances).
 //
 // Kernel instances ("kinds", one translation unit each): kind 0 reads
 // stencil neighbours through the caches, with a tile of 1..4 planes per
 // patch; the staged kinds stage each grid function's tile neighbourhood in
 // LDS (bssn_lds.h: ASrc for 4th order, HSrc for the wider neighbourhood of
 // 6th and 8th order) with one single-plane tile shape each: 32x8 (kinds 1,
-// 3, 4 for orders 4, 6, 8) or 16x16 (kinds 2, 5, 6).  The autotuner
+// 3, 4 for orders 4, 6, 8) or 16x16 (kinds 2, 5, 6); kind 7 stages 4th
+// order in z-blocked 32x8x2 tiles (bssn_zsrc.h; mixed precision without
+// dissipation, where the point code fits two waves per SIMD).  The autotuner
 // (chemora_autotune) picks the tile of kind 0 per size class of patches,
 // pruning the candidates with a performance model (model_time) and timing
 // the survivors, then times the candidate kinds of the batch's order over
@@ -108,7 +114,13 @@ int staged_kind(int order, bool square) {
 }
 
 Tile kind_shape(int kind) {
+  if (kind == 7) return Tile{32, 8, 2};
   return (kind == 2 || kind == 5 || kind == 6) ? Tile{16, 16, 1} : Tile{32, 8, 1};
+}
+
+// the z-blocked kind runs mixed-precision 4th-order batches without dissipation
+bool zblocked_ok(int precision, int order, bool ko) {
+  return precision == CHEMORA_MIXED && order == 4 && !ko;
 }
 
 std::mutex g_table_mu;
@@ -119,17 +131,21 @@ std::map<std::pair<int, int>, int> g_kind;
 
 // Kernel kind of a new plan.  CHEMORA_BATCH_KIND (ablation switch, read at
 // every plan build): 0 = kind 0 (4th order; other orders: 32x8 staged),
-// 1 = the 32x8 staged kind of the order, 2 = its 16x16 staged kind.
-// Otherwise the tuned kind, else the 32x8 staged kind.
-int plan_kind(int precision, int order) {
+// 1 = the 32x8 staged kind of the order, 2 = its 16x16 staged kind, 3 = the
+// z-blocked kind where it applies (else 32x8 staged).  Otherwise the tuned
+// kind, else the 32x8 staged kind.
+int plan_kind(int precision, int order, bool ko) {
   const char* e = std::getenv("CHEMORA_BATCH_KIND");
-  if (e && (e[0] == '0' || e[0] == '1' || e[0] == '2') && e[1] == 0) {
+  if (e && e[0] >= '0' && e[0] <= '3' && e[1] == 0) {
     if (e[0] == '0') return order == 4 ? 0 : staged_kind(order, false);
+    if (e[0] == '3') return zblocked_ok(precision, order, ko) ? 7 : staged_kind(order, false);
     return staged_kind(order, e[0] == '2');
   }
   std::lock_guard<std::mutex> lk(g_table_mu);
   auto it = g_kind.find({precision, order});
-  return it != g_kind.end() ? it->second : staged_kind(order, false);
+  if (it != g_kind.end() && (it->second != 7 || zblocked_ok(precision, order, ko)))
+    return it->second;
+  return staged_kind(order, false);
 }
 
 int compute_units() {
@@ -151,6 +167,7 @@ int per_cu(int precision, int kind, bool ko, bool par = false) {
     case 4: return batch_per_cu<4>(precision, ko, par);
     case 5: return batch_per_cu<5>(precision, ko, par);
     case 6: return batch_per_cu<6>(precision, ko, par);
+    case 7: return batch_per_cu<7>(precision, ko, par);
     default: return batch_per_cu<1>(precision, ko, par);
   }
 }
@@ -175,13 +192,17 @@ int persistent_blocks(int precision, int kind, bool ko, bool par = false) {
 //    1 for the staged kinds.
 //  * Ghost item: its points / 64 waves x 0.25 (closed-form evaluation and
 //    stores, no stencils).
-//  * Schedule: the kernel's own static assignment -- XCD x takes share x of
-//    the interior items and of the ghost items, in list order, and its
-//    grid / 8 workgroups take every (grid / 8)-th item of the share.
+//  * Schedule: XCD x takes share x of the interior items and of the ghost
+//    items, in list order.  Persistent instances: its grid / 8 workgroups
+//    take every (grid / 8)-th item of the share (static).  One item per
+//    workgroup: the hardware hands the share's items, in order, to
+//    whichever of the XCD's grid / 8 resident slots frees first (greedy
+//    list scheduling).
 //  * Occupancy: grid = resident workgroups per CU (k) x CUs; the k
 //    workgroups of a CU share it, so a launch lasts the largest
-//    per-workgroup load x k / min(k, 2) (a 256-thread workgroup is one wave
-//    per SIMD; latency hiding saturates at two waves per SIMD).
+//    per-workgroup load x k / min(w, 2), w = k x (waves per SIMD of one
+//    workgroup: 1 for 256 threads, 2 for the z-blocked kind's 512) --
+//    latency hiding saturates at two waves per SIMD.
 // halo factor times the kind's per-point cost
 double halo_factor(int kind, const Tile& t, int order) {
   const double pts = (double)t.ltx * t.lty * t.tz;
@@ -189,6 +210,8 @@ double halo_factor(int kind, const Tile& t, int order) {
   double reads;
   if (kind == 0)
     reads = (t.ltx + 2.0 * r) * (t.lty + 2.0 * r) * (t.tz + 2.0 * r);
+  else if (kind == 7)  // planes -2 .. tz+1 with halo, the two outer planes without
+    reads = (t.tz + 4.0) * (t.ltx + 2.0 * r) * (t.lty + 2.0 * r) + 2.0 * t.ltx * t.lty;
   else
     reads = (t.ltx + 2.0 * r) * (t.lty + 2.0 * r) + 2.0 * (r - 1) * (t.ltx + 2.0 * r - 2) *
             (t.lty + 2.0 * r - 2) + 2.0 * t.ltx * t.lty;
@@ -218,7 +241,7 @@ std::vector<int> list_order(const std::vector<ModelPatch>& ps) {
 }
 
 double model_time(const std::vector<ModelPatch>& ps, const std::vector<Tile>& tiles, int kind,
-                  int order, int k_per_cu, int grid, bool ghosts) {
+                  int order, int k_per_cu, int grid, bool ghosts, bool dynamic) {
   std::vector<double> items, gitems;
   for (int q : list_order(ps)) {
     const Tile& t = tiles[q];
@@ -239,11 +262,17 @@ double model_time(const std::vector<ModelPatch>& ps, const std::vector<Tile>& ti
     const long long i0 = ni * x / kNumXcd, i1 = ni * (x + 1) / kNumXcd;
     const long long g0 = ng * x / kNumXcd, g1 = ng * (x + 1) / kNumXcd;
     const long long share = (i1 - i0) + (g1 - g0);
-    for (long long t = 0; t < share; ++t)
-      load[t % R] += t < i1 - i0 ? items[i0 + t] : gitems[g0 + t - (i1 - i0)];
+    for (long long t = 0; t < share; ++t) {
+      const double c = t < i1 - i0 ? items[i0 + t] : gitems[g0 + t - (i1 - i0)];
+      if (dynamic)  // the slot that frees first takes the next item
+        *std::min_element(load.begin(), load.end()) += c;
+      else
+        load[t % R] += c;
+    }
     for (double l : load) worst = std::max(worst, l);
   }
-  return worst * k_per_cu / std::min(k_per_cu, 2);
+  const double w = k_per_cu * (kind == 7 ? 2.0 : 1.0);
+  return worst * k_per_cu / std::min(w, 2.0);
 }
 
 // model-best kind 0 tile of one patch with one plane per item (untuned
@@ -440,7 +469,14 @@ int build_plan(Plan* P, const chemora_patch* patches, int32_t np, void* meta, do
     e = hipMemcpy(m + MetaLayout::gprefix_off(np), gprefix.data(), 8 * (np + 1),
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) return device_status(e, "batch plan upload");
-  P->grid_blocks = persistent_blocks(precision, kind, P->ko, P->has_parents);
+  if (batch_persistent_host(precision, kind)) {
+    P->grid_blocks = persistent_blocks(precision, kind, P->ko, P->has_parents);
+  } else {  // one workgroup per item of the largest XCD share
+    const long long ng = P->n_total - P->n_interior;
+    const long long per = (P->n_interior + kNumXcd - 1) / kNumXcd + (ng + kNumXcd - 1) / kNumXcd;
+    if (per * kNumXcd > 0x7fffffffLL) return fail(CHEMORA_ERR_INVALID, "batch too large");
+    P->grid_blocks = (int)std::max<long long>(kNumXcd, per * kNumXcd);
+  }
   const double tout[5] = {0.0, 0.5, 0.5, 1.0, 1.0};
   for (int s = 0; s <= 4; ++s) {
     Batch& b = P->batch[s];
@@ -480,6 +516,7 @@ hipError_t launch_any(const Plan* P, int s, hipStream_t st) {
     case 4: return launch_batch_kind<4>(P->precision, P->ko, par, s, b, g, st);
     case 5: return launch_batch_kind<5>(P->precision, P->ko, par, s, b, g, st);
     case 6: return launch_batch_kind<6>(P->precision, P->ko, par, s, b, g, st);
+    case 7: return launch_batch_kind<7>(P->precision, P->ko, par, s, b, g, st);
     default: return launch_batch_kind<1>(P->precision, P->ko, par, s, b, g, st);
   }
 }
@@ -506,12 +543,18 @@ int capture_graph(Plan* P) {
   return device_status(e, "batch graph capture");
 }
 
-// Time three right-hand-side launches (stage 0 writes the first stage buffer;
-// states are untouched) of a plan after one warm-up launch.
+// Time three launches of the second substage of a plan (what a step runs:
+// stencils, the RK update and the ghost items; it reads the first stage
+// buffer and the state and writes only the workspace, so the patches' states
+// are untouched), after a right-hand-side launch that fills the first stage
+// buffer and a warm-up launch.  The clock is set to 0 for the ghost items.
 int time_plan(const Plan* P, hipEvent_t e0, hipEvent_t e1, float* ms) {
-  hipError_t e = launch_any(P, 0, nullptr);
+  hipLaunchKernelGGL(set_clock_kernel, dim3(1), dim3(1), 0, nullptr, P->batch[2].clock, 0.0);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_any(P, 0, nullptr);
+  if (e == hipSuccess) e = launch_any(P, 2, nullptr);
   if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
-  for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_any(P, 0, nullptr);
+  for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_any(P, 2, nullptr);
   if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
@@ -634,7 +677,9 @@ int chemora_batch_step_levels(const chemora_patch* patches, const chemora_parent
         delete P;
         return device_status(e, "batch plan");
       }
-      const int kind = plan_kind(precision, order);
+      bool ko = false;
+      for (int q = 0; q < npatches; ++q) ko = ko || grid_par(patches[q].grid).ko_sigma != 0.0;
+      const int kind = plan_kind(precision, order, ko);
       st = build_plan(P, patches, npatches, meta, dt, precision, kind,
                       kind_tiles(kind, precision, patches, npatches), par, off.data());
       if (st == CHEMORA_OK) st = capture_graph(P);
@@ -693,7 +738,7 @@ int chemora_batch_release(void* meta) {
 int chemora_batch_tile(const int32_t n[3], int32_t precision, int32_t tile[3]) {
   if (!n || !tile) return fail(CHEMORA_ERR_INVALID, "NULL argument");
   if (n[0] < 1 || n[1] < 1 || n[2] < 1) return fail(CHEMORA_ERR_INVALID, "n must be >= 1");
-  const Tile t = kind_tile(plan_kind(precision, 4), precision, n);
+  const Tile t = kind_tile(plan_kind(precision, 4, false), precision, n);
   tile[0] = t.ltx;
   tile[1] = t.lty;
   tile[2] = t.tz;
@@ -745,7 +790,7 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
       std::vector<std::pair<double, Tile>> scored;
       for (const Tile& t : kCandidates)
         scored.push_back({model_time(cmodel[kv.first], std::vector<Tile>(ps.size(), t), 0, order,
-                                     k, grid, false),
+                                     k, grid, false, !batch_persistent_host(precision, 0)),
                           t});
       std::stable_sort(scored.begin(), scored.end(),
                        [](const std::pair<double, Tile>& a, const std::pair<double, Tile>& b) {
@@ -762,7 +807,7 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
         if (st == CHEMORA_OK) st = time_plan(&P, e0, e1, &ms);
         if (st != CHEMORA_OK) break;
         snprintf(buf, sizeof buf,
-                 "%s{\"tile\": [%d, %d, %d], \"model\": %.1f, \"ms_per_rhs\": %.5f}", c ? ", " : "",
+                 "%s{\"tile\": [%d, %d, %d], \"model\": %.1f, \"ms_per_substage\": %.5f}", c ? ", " : "",
                  scored[c].second.ltx, scored[c].second.lty, scored[c].second.tz, scored[c].first,
                  ms / 3.0);
         trials += buf;
@@ -788,19 +833,21 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
   // and measured time; the untuned default is the 32x8 staged kind
   std::vector<int> kinds = {staged_kind(order, false), staged_kind(order, true)};
   if (order == 4) kinds.insert(kinds.begin(), 0);
+  if (zblocked_ok(precision, order, ko)) kinds.push_back(7);
   std::map<int, float> kind_ms;
   std::string ks;
   for (int kind : kinds) {
     if (st != CHEMORA_OK) break;
     const std::vector<Tile> tiles = kind_tiles(kind, precision, patches, npatches);
     const double model = model_time(all, tiles, kind, order, per_cu(precision, kind, ko),
-                                    persistent_blocks(precision, kind, ko), false);
+                                    persistent_blocks(precision, kind, ko), false,
+                                    !batch_persistent_host(precision, kind));
     Plan P;
     st = build_plan(&P, patches, npatches, meta, 0.0, precision, kind, tiles);
     float ms = 0.f;
     if (st == CHEMORA_OK) st = time_plan(&P, e0, e1, &ms);
     kind_ms[kind] = ms;
-    snprintf(buf, sizeof buf, "%s\"%d\": {\"model\": %.1f, \"per_cu\": %d, \"ms_per_rhs\": %.5f}",
+    snprintf(buf, sizeof buf, "%s\"%d\": {\"model\": %.1f, \"per_cu\": %d, \"ms_per_substage\": %.5f}",
              ks.empty() ? "" : ", ", kind, model, per_cu(precision, kind, ko), ms / 3.0);
     ks += buf;
   }
@@ -814,7 +861,7 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
     }
     snprintf(buf, sizeof buf,
              "  \"precision%d_order%d_kind\": {\"kind\": %d, \"untuned_kind\": %d, "
-             "\"tuned_ms_per_rhs\": %.5f, \"untuned_ms_per_rhs\": %.5f, \"kinds\": {",
+             "\"tuned_ms_per_substage\": %.5f, \"untuned_ms_per_substage\": %.5f, \"kinds\": {",
              precision, order, best_kind, staged_kind(order, false), kind_ms[best_kind] / 3.0,
              kind_ms[staged_kind(order, false)] / 3.0);
     json += buf;
@@ -835,11 +882,11 @@ int chemora_autotune(const chemora_patch* patches, int32_t npatches, void* meta,
 
 int chemora_batch_model(const int32_t* dims, const int32_t* tiles, int32_t npatches,
                         int32_t kind, int32_t fd_order, int32_t per_cu_wg, int32_t grid,
-                        int32_t ghost_width, double* out) {
+                        int32_t ghost_width, int32_t per_item, double* out) {
   if (!dims || !tiles || !out) return fail(CHEMORA_ERR_INVALID, "NULL argument");
   if (npatches < 1 || npatches > kMaxPatches)
     return fail(CHEMORA_ERR_INVALID, "npatches must be in [1, %d]", kMaxPatches);
-  if (kind < 0 || kind >= kNumKinds) return fail(CHEMORA_ERR_INVALID, "kind must be in [0, 6]");
+  if (kind < 0 || kind >= kNumKinds) return fail(CHEMORA_ERR_INVALID, "kind must be in [0, 7]");
   if (fd_order != 4 && fd_order != 6 && fd_order != 8)
     return fail(CHEMORA_ERR_INVALID, "fd_order must be 4, 6 or 8");
   if (per_cu_wg < 1 || grid < 1 || ghost_width < 0)
@@ -857,7 +904,7 @@ int chemora_batch_model(const int32_t* dims, const int32_t* tiles, int32_t npatc
                        ghost_width > 0 ? ghost_points(G) : 0};
     ts[q] = Tile{tiles[3 * q], tiles[3 * q + 1], tiles[3 * q + 2]};
   }
-  *out = model_time(ps, ts, kind, fd_order, per_cu_wg, grid, ghost_width > 0);
+  *out = model_time(ps, ts, kind, fd_order, per_cu_wg, grid, ghost_width > 0, per_item != 0);
   return CHEMORA_OK;
 }
 

@@ -1,6 +1,6 @@
 // batch_kernel.h -- data structures and device helpers of the batched patch
 // path (batch.hip), shared by its host code and by the translation units
-// that instantiate the persistent stage kernel (batch_stage.h, one unit per
+// that instantiate the stage kernel (batch_stage.h, one unit per
 // kernel kind, so that they compile in parallel).
 #pragma once
 
@@ -203,11 +203,19 @@ __device__ __forceinline__ void stage_buffers(const Batch& B, const PatchDesc& p
 //   kinds 1 / 2: LDS-staged 4th order, 32x8 / 16x16 single-plane tiles
 //   kinds 3 / 5: LDS-staged 6th order, 32x8 / 16x16
 //   kinds 4 / 6: LDS-staged 8th order, 32x8 / 16x16
+//   kind 7: LDS-staged 4th order, z-blocked 32x8x2 tiles (mixed precision,
+//     no dissipation)
 // launch_batch_kind<K>: one substage (0 = right-hand side only, 1..4) over
 // the work list of b on grid workgroups, the instance with prolongation
 // ghost items when par; batch_per_cu<K>: resident workgroups per CU of that
 // instance (its registers and LDS decide).
-constexpr int kNumKinds = 7;
+constexpr int kNumKinds = 8;
+// host side of batch_persistent (batch_stage.h): FP64 kinds 0-2 stride
+// their share with a resident grid, every other instance takes one item per
+// workgroup
+inline bool batch_persistent_host(int precision, int kind) {
+  return precision == CHEMORA_FP64 && kind <= 2;
+}
 template <int K>
 hipError_t launch_batch_kind(int precision, bool ko, bool par, int stage, const Batch& b,
                              unsigned grid, hipStream_t s);
@@ -226,6 +234,7 @@ CHEMORA_BATCH_KIND_DECL(3)
 CHEMORA_BATCH_KIND_DECL(4)
 CHEMORA_BATCH_KIND_DECL(5)
 CHEMORA_BATCH_KIND_DECL(6)
+CHEMORA_BATCH_KIND_DECL(7)
 #undef CHEMORA_BATCH_KIND_DECL
 
 }  // namespace chemora

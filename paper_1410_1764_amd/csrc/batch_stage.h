@@ -1,4 +1,4 @@
-// batch_stage.h -- the persistent stage kernel of the batched patch path.
+// batch_stage.h -- the stage kernel of the batched patch path.
 // Included by one translation unit per kernel kind (batch_k*.hip), each of
 // which instantiates its kind for both precisions and the substages.
 //
@@ -11,22 +11,32 @@
 // and spills in FP64.
 #pragma once
 
+#include <type_traits>
+
 #include "batch_kernel.h"
+#include "bssn_zsrc.h"
 
 namespace chemora {
 namespace {
 
 // Kernel kinds: 0 = cached loads (tile per patch); staged single-plane
 // tiles 1 = 4th order 32x8, 2 = 4th order 16x16, 3 = 6th order 32x8,
-// 4 = 8th order 32x8, 5 = 6th order 16x16, 6 = 8th order 16x16.
+// 4 = 8th order 32x8, 5 = 6th order 16x16, 6 = 8th order 16x16;
+// 7 = 4th order, z-blocked 32x8x2 tiles of 512 threads (bssn_zsrc.h: the
+// staging of the single-grid z-blocked kernels; mixed precision without
+// dissipation, where the fused point code fits two waves per SIMD).
 template <int KIND>
 struct KindShape {
-  static constexpr bool WIDE = KIND == 1 || KIND == 3 || KIND == 4;
-  static constexpr int TX = WIDE ? 32 : 16, TY = WIDE ? 8 : 16;
+  static constexpr bool ZB = KIND == 7;
+  static constexpr bool WIDE = KIND == 1 || KIND == 3 || KIND == 4 || ZB;
+  static constexpr int TX = WIDE ? 32 : 16, TY = WIDE ? 8 : 16, TZ = ZB ? 2 : 1;
+  static constexpr int NT = ZB ? 512 : kThreads;  // threads per workgroup
+  static constexpr int WPE = ZB ? 2 : 1;          // waves per SIMD the registers must allow
   static constexpr int ORD = (KIND == 3 || KIND == 5) ? 6 : ((KIND == 4 || KIND == 6) ? 8 : 4);
   static constexpr bool HI = ORD != 4;
   // kind 0: its first two buffers hold the prolongation ghost boxes only
   static constexpr int TOT = KIND == 0 ? kBatchProlongLds
+                             : ZB      ? ZShape<TX, TY, TZ>::TOTAL
                              : HI      ? HShape<TX, TY, ORD / 2 + 1>::TOTAL
                                        : LdsShape<TX, TY>::TOTAL;
   static constexpr int TOT3 = (HI || KIND == 0) ? 1 : TOT;  // third buffer: async kinds only
@@ -83,12 +93,43 @@ __device__ __forceinline__ void staged_tile(const PatchDesc& p, const StageIO& i
                          false, p.P.enforce != 0);
 }
 
+// whether the kernel instance of type T and kind KIND is persistent (the
+// host sizes the grid to match: batch_persistent_host)
+template <typename T, int KIND>
+constexpr bool batch_persistent() {
+  return std::is_same<T, double>::value && KIND <= 2;
+}
+
+// one 32 x 8 x 2 tile of the z-blocked kind: thread (tx, ty, pz) evaluates
+// plane k0 + pz
+template <int STAGE, typename T, int KOM>
+__device__ __forceinline__ void zblocked_tile(const PatchDesc& p, const StageIO& io,
+                                              long long tile, double* const* bufs) {
+  using K = KindShape<7>;
+  const Geo& G = p.G;
+  int bx, by, bz;
+  patch_tile(p, tile, bx, by, bz);
+  const int t = (int)threadIdx.x;
+  const int tx = t % K::TX, ty = (t / K::TX) % K::TY, pz = t / (K::TX * K::TY);
+  const int x0 = bx * K::TX, y0 = by * K::TY, k0 = bz * K::TZ;
+  const int i = x0 + tx, j = y0 + ty, k = k0 + pz;
+  ZSrc<K::TX, K::TY, K::TZ, kBatchBufs, RhsOrder> src;
+  src.init(G, io.yin, bufs, x0, y0, k0, tx, ty, pz);
+  T rhs[V_N];
+  bssn_rhs_point<T, KOM>(src, p.W, p.P, rhs);
+  if (i < G.n[0] && j < G.n[1] && k < G.n[2])
+    bssn_store<STAGE, T>(io, G, i + (long long)j * G.sy + (long long)k * G.sz, i, j, k, rhs,
+                         false, p.P.enforce != 0);
+}
+
 // KOM: Kreiss-Oliger dissipation compiled in (KO_ON: patches with sigma = 0
 // add an exact zero) or out (KO_OFF: no patch dissipates)
 // PAR: some patch of the batch has a coarse parent (prolongation ghost
 // items compiled in; 4th-order kinds only)
 template <int STAGE, typename T, int KIND, int KOM, bool PAR>
-__global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
+__global__ void __launch_bounds__(KindShape<KIND>::NT)
+__attribute__((amdgpu_waves_per_eu(KindShape<KIND>::WPE))) batch_stage_kernel(Batch B) {
+  constexpr int NT = KindShape<KIND>::NT;
   __shared__ int s_patch;
   constexpr int TOT = KindShape<KIND>::TOT;
   // separate arrays, one per staging buffer (see bssn_lds.h); a tiny
@@ -117,7 +158,17 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
     s_lo = 0;
     s_hi = -1;
   }
-  for (long long t = blockIdx.x / kNumXcd; t < share; t += R) {
+  // Persistent (a workgroup strides its XCD's share) only where that
+  // measured faster: FP64 at 4th order, whose point code holds one wave per
+  // SIMD either way.  Elsewhere the grid gives every item of a share its own
+  // workgroup (the hardware hands them out in order), so the item loop runs
+  // once -- provably so for the compiler, which would otherwise hoist
+  // thread-invariant values out of the loop and hold them through the point
+  // code: mixed kinds 1/2 took 256 VGPRs + 96 AGPRs (one wave per SIMD)
+  // against 241 VGPRs (two), the z-blocked kind spilled ~300 B per lane and
+  // the FP64 high-order kinds 144-548 B.
+  const long long step = batch_persistent<T, KIND>() ? R : share;
+  for (long long t = blockIdx.x / kNumXcd; t < share; t += step) {
     const bool interior = t < i1 - i0;
     const long long item = interior ? i0 + t : ni + g0 + (t - (i1 - i0));
     __syncthreads();  // the previous item is finished by every wave
@@ -140,7 +191,7 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
       const unsigned long long* from =
           reinterpret_cast<const unsigned long long*>(B.pd + s_patch);
       unsigned long long* to = reinterpret_cast<unsigned long long*>(&s_pd);
-      for (int w = (int)threadIdx.x; w < (int)(sizeof(PatchDesc) / 8); w += kThreads)
+      for (int w = (int)threadIdx.x; w < (int)(sizeof(PatchDesc) / 8); w += NT)
         to[w] = from[w];
       __syncthreads();
     }
@@ -150,7 +201,9 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
     stage_buffers(B, p, B.stage_io, io, B.dt);
     if (interior) {
       const long long tile = item - B.prefix[s_patch];
-      if constexpr (KIND != 0) {
+      if constexpr (KindShape<KIND>::ZB) {
+        zblocked_tile<STAGE, T, KOM>(p, io, tile, bufs);
+      } else if constexpr (KIND != 0) {
         staged_tile<STAGE, T, KIND, KOM>(p, io, tile, bufs, TB);
       } else {
         int tx, ty, tzi;
@@ -179,7 +232,7 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
         }
       }
       for (long long gq = chunk * kGhostChunk + threadIdx.x;
-           gq < min((chunk + 1) * kGhostChunk, p.ghosts); gq += kThreads) {
+           gq < min((chunk + 1) * kGhostChunk, p.ghosts); gq += NT) {
         int ijk[3];
         ghost_ijk(G, gq, ijk);
         const int a = p.P.gw_axis;
@@ -193,7 +246,7 @@ __global__ void __launch_bounds__(kThreads) batch_stage_kernel(Batch B) {
 
 template <typename T, int KIND, int KOM, bool PAR>
 hipError_t launch_stage_t(int stage, const Batch& b, unsigned grid, hipStream_t st) {
-  const dim3 g(grid), blk(kThreads);
+  const dim3 g(grid), blk(KindShape<KIND>::NT);
   switch (stage) {
     case 0: hipLaunchKernelGGL((batch_stage_kernel<0, T, KIND, KOM, PAR>), g, blk, 0, st, b); break;
     case 1: hipLaunchKernelGGL((batch_stage_kernel<1, T, KIND, KOM, PAR>), g, blk, 0, st, b); break;
@@ -217,21 +270,27 @@ hipError_t launch_stage_p(bool par, int stage, const Batch& b, unsigned grid, hi
 template <int KIND>
 hipError_t launch_stage_kind(int precision, bool ko, bool par, int stage, const Batch& b,
                              unsigned grid, hipStream_t st) {
-  if constexpr (!KindShape<KIND>::HI) {
-    if (ko)
-      return precision == CHEMORA_MIXED
-                 ? launch_stage_p<float, KIND, KO_ON>(par, stage, b, grid, st)
-                 : launch_stage_p<double, KIND, KO_ON>(par, stage, b, grid, st);
+  if constexpr (KindShape<KIND>::ZB) {  // mixed precision without dissipation only
+    if (precision != CHEMORA_MIXED || ko) return hipErrorInvalidValue;
+    return launch_stage_p<float, KIND, KO_OFF>(par, stage, b, grid, st);
+  } else {
+    if constexpr (!KindShape<KIND>::HI) {
+      if (ko)
+        return precision == CHEMORA_MIXED
+                   ? launch_stage_p<float, KIND, KO_ON>(par, stage, b, grid, st)
+                   : launch_stage_p<double, KIND, KO_ON>(par, stage, b, grid, st);
+    }
+    return precision == CHEMORA_MIXED
+               ? launch_stage_p<float, KIND, KO_OFF>(par, stage, b, grid, st)
+               : launch_stage_p<double, KIND, KO_OFF>(par, stage, b, grid, st);
   }
-  return precision == CHEMORA_MIXED ? launch_stage_p<float, KIND, KO_OFF>(par, stage, b, grid, st)
-                                    : launch_stage_p<double, KIND, KO_OFF>(par, stage, b, grid, st);
 }
 
 template <typename T, int KIND, int KOM, bool PAR>
 int per_cu_t() {
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_stage_kernel<1, T, KIND, KOM, PAR>,
-                                                   kThreads, 0) != hipSuccess || n < 1)
+                                                   KindShape<KIND>::NT, 0) != hipSuccess || n < 1)
     n = 1;
   return n;
 }
@@ -246,12 +305,16 @@ int per_cu_p(bool par) {
 
 template <int KIND>
 int per_cu_kind(int precision, bool ko, bool par) {
-  if constexpr (!KindShape<KIND>::HI) {
-    if (ko) return precision == CHEMORA_MIXED ? per_cu_p<float, KIND, KO_ON>(par)
-                                              : per_cu_p<double, KIND, KO_ON>(par);
+  if constexpr (KindShape<KIND>::ZB) {
+    return per_cu_p<float, KIND, KO_OFF>(par);
+  } else {
+    if constexpr (!KindShape<KIND>::HI) {
+      if (ko) return precision == CHEMORA_MIXED ? per_cu_p<float, KIND, KO_ON>(par)
+                                                : per_cu_p<double, KIND, KO_ON>(par);
+    }
+    return precision == CHEMORA_MIXED ? per_cu_p<float, KIND, KO_OFF>(par)
+                                      : per_cu_p<double, KIND, KO_OFF>(par);
   }
-  return precision == CHEMORA_MIXED ? per_cu_p<float, KIND, KO_OFF>(par)
-                                    : per_cu_p<double, KIND, KO_OFF>(par);
 }
 
 }  // namespace

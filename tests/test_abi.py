@@ -272,8 +272,17 @@ def test_batch_model_wave_quantisation_and_schedule():
     assert C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=1, grid=8, ghost_width=3) > one
     # the cached-load kind is priced above the staged kinds per point
     assert C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=0, grid=8) > one
+    # one item per workgroup: the greedy hand-out balances what the static
+    # stride cannot (a long item first, then short ones)
+    mixed = [(32, 8, 16), (32, 8, 1), (32, 8, 1), (32, 8, 1)]
+    tiles = [(32, 8, 1)] * 4
+    stat = C.batch_model(mixed, tiles, kind=1, grid=16)
+    dyn = C.batch_model(mixed, tiles, kind=1, grid=16, per_item=True)
+    assert dyn <= stat
+    assert C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=1, grid=8, per_item=True) \
+        == pytest.approx(one)
     with pytest.raises(C.ChemoraError):
-        C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=7)
+        C.batch_model([(64, 64, 8)], [(32, 8, 1)], kind=8)
 
 
 def test_batch_parent_validation_without_a_device():

@@ -120,11 +120,12 @@ def test_batch_high_order_matches_oracle(order, precision, tol, shape, monkeypat
     C.batch_release(meta)
 
 
-@pytest.mark.parametrize("kind", ["0", "1", "2"])
+@pytest.mark.parametrize("kind", ["0", "1", "2", "3"])
 @pytest.mark.parametrize("precision,tol", [(C.FP64, 1e-12), (C.MIXED, 1e-5)])
 def test_batch_kernel_kinds_match_oracle(kind, precision, tol, monkeypatch):
     """Each kernel kind (per-patch cached-load tiles; LDS-staged 32x8 and
-    16x16 tiles) on uneven patches whose sizes leave ragged tiles."""
+    16x16 tiles; z-blocked 32x8x2 tiles, which FP64 batches replace by 32x8)
+    on uneven patches whose sizes leave ragged tiles."""
     monkeypatch.setenv("CHEMORA_BATCH_KIND", kind)
     specs = SMALL[:2] + [{"n": (19, 13, 11), "h": 1 / 64, "origin": (0.7, 0.1, 0.4)}]
     grids, blocks, states, wss, y0s = _patches(specs, precision, seed=11)

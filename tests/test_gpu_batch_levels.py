@@ -5,7 +5,7 @@ ghost item per box of its ghost shell, from three time levels of a coarse
 parent, at the stage's time.  Each patch against the oracle's RK4 with the
 same prolongated ghosts (orc_rk4_prolong), interior and ghosts; patches with
 analytic ghosts in the same batch against the oracle's analytic RK4; both
-precisions, the three 4th-order kernel kinds, plan reuse and graph replays
+precisions, the 4th-order kernel kinds, plan reuse and graph replays
 across calls; argument checks."""
 import numpy as np
 import pytest
@@ -96,7 +96,7 @@ def _check(S, nsteps, dt, tol, label):
         assert eg <= max(tol, 1e-14)
 
 
-@pytest.mark.parametrize("kind", ["0", "1", "2"])
+@pytest.mark.parametrize("kind", ["0", "1", "2", "3"])
 @pytest.mark.parametrize("precision,tol", [(C.FP64, 1e-12), (C.MIXED, 1e-5)])
 def test_batch_with_parents_matches_oracle(kind, precision, tol, monkeypatch):
     monkeypatch.setenv("CHEMORA_BATCH_KIND", kind)
