@@ -25,7 +25,10 @@
 // The intermediates go to the interior of a state-sized buffer (StageIO::tmp,
 // default the stage output): each thread of the rest kernel reads its own
 // point's values before it writes any value of that point, so the output
-// can hold them.  Every term is computed with the fused kernel's arithmetic
+// can hold them.  They are written and read once each, with nontemporal
+// stores and loads (st_stream / ld_stream), so that they pass through L2
+// without evicting the staged grid functions that neighbouring workgroups
+// still read.  Every term is computed with the fused kernel's arithmetic
 // in the same order (sums of the same two operands may swap sides).
 #include <cstdlib>
 #include <cstring>
@@ -119,7 +122,7 @@ __device__ __forceinline__ void bssn_curv_point(Src& src, const Weights& w, Stas
   const T chi = (T)src.center(V_CHI);
   if (active) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) o[(I_GD + d) * sv] = (double)Gd[d];
+    for (int d = 0; d < 3; ++d) st_stream(&o[(I_GD + d) * sv], (double)Gd[d]);
   }
 
   T dd[6], dpure[3], adv;
@@ -130,7 +133,7 @@ __device__ __forceinline__ void bssn_curv_point(Src& src, const Weights& w, Stas
     const auto f = src.acquire(V_ALP);
     alpha = (T)f(0, 0, 0);  // the staged centre: not held through the geometry
     axis_derivs<T, true, true, true, KOM, 4>(f, w, bpos, beta, dalp, dpure, adv);
-    if (active) o[V_ALP * sv] = (double)adv;
+    if (active) st_stream(&o[V_ALP * sv], (double)adv);
     second_derivs<T, 4>(f, w, dpure, dd);
     const T i2chi = (T)0.5 / chi;
     T uchi[3];
@@ -192,7 +195,7 @@ __device__ __forceinline__ void bssn_curv_point(Src& src, const Weights& w, Stas
                    (T)2 * (cdu[i][1] * Atu[1] + cdu[i][2] * Atu[2] + cdu[i][4] * Atu[4]);
       T Gs = (T)(-2) * aal + (T)2 * alpha * (cA - (T)1.5 * ach * ichi);
       pin(Gs);
-      if (active) o[(I_GS + i) * sv] = (double)Gs;
+      if (active) st_stream(&o[(I_GS + i) * sv], (double)Gs);
     }
     fence_memory();
   }
@@ -205,7 +208,7 @@ __device__ __forceinline__ void bssn_curv_point(Src& src, const Weights& w, Stas
       for (int j = 0; j < 3; ++j) AtAt += Atm[i][j] * Atm[j][i];
     T rK = -lapalp + alpha * (AtAt + trK * trK * third);
     pin(rK);
-    if (active) o[I_RK * sv] = (double)rK;
+    if (active) st_stream(&o[I_RK * sv], (double)rK);
     fence_memory();
   }
   const T trX = gu[0] * X[0] + gu[3] * X[3] + gu[5] * X[5] +
@@ -219,14 +222,14 @@ __device__ __forceinline__ void bssn_curv_point(Src& src, const Weights& w, Stas
 #pragma unroll
       for (int k = 0; k < 3; ++k) aa += At[sidx(i, k)] * Atm[k][j];
       T rA = chi * (X[q] - gt[q] * trX * third) + alpha * (trK * At[q] - (T)2 * aa);
-      if (active) o[(I_RA + q) * sv] = (double)rA;
+      if (active) st_stream(&o[(I_RA + q) * sv], (double)rA);
     }
   if (active) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) o[(V_GT + q) * sv] = (double)adv10[V_GT + q];
+    for (int q = 0; q < 6; ++q) st_stream(&o[(V_GT + q) * sv], (double)adv10[V_GT + q]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) o[(V_GAM + d) * sv] = (double)adv10[V_GAM + d];
-    o[V_CHI * sv] = (double)adv10[V_CHI];
+    for (int d = 0; d < 3; ++d) st_stream(&o[(V_GAM + d) * sv], (double)adv10[V_GAM + d]);
+    st_stream(&o[V_CHI * sv], (double)adv10[V_CHI]);
   }
 }
 
@@ -253,10 +256,10 @@ __device__ __forceinline__ void bssn_rest_point(Src& src, const double* I, long 
   T Gs[3], Gd[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    Gs[i] = (T)I[(I_GS + i) * sv];
-    Gd[i] = (T)I[(I_GD + i) * sv];
+    Gs[i] = (T)ld_stream(&I[(I_GS + i) * sv]);
+    Gd[i] = (T)ld_stream(&I[(I_GD + i) * sv]);
   }
-  const T rK = (T)I[I_RK * sv];
+  const T rK = (T)ld_stream(&I[I_RK * sv]);
   T gu[6];
   inverse_metric(gt, gu);
 
@@ -331,16 +334,16 @@ __device__ __forceinline__ void bssn_rest_point(Src& src, const double* I, long 
   // every grid function is staged: the remaining intermediates
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    rhs[V_GT + q] = (T)I[(V_GT + q) * sv] + rhs[V_GT + q];
-    const T rA = (T)I[(I_RA + q) * sv] + sA[q];
+    rhs[V_GT + q] = (T)ld_stream(&I[(V_GT + q) * sv]) + rhs[V_GT + q];
+    const T rA = (T)ld_stream(&I[(I_RA + q) * sv]) + sA[q];
     rhs[V_AT + q] = rhs[V_AT + q] + rA;
   }
-  rhs[V_CHI] = (T)I[V_CHI * sv];
+  rhs[V_CHI] = (T)ld_stream(&I[V_CHI * sv]);
   rhs[V_CHI] += two3 * chi * (alpha * trK - divb);
-  rhs[V_ALP] = (T)I[V_ALP * sv];
+  rhs[V_ALP] = (T)ld_stream(&I[V_ALP * sv]);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    rhs[V_GAM + i] = (T)I[(V_GAM + i) * sv];
+    rhs[V_GAM + i] = (T)ld_stream(&I[(V_GAM + i) * sv]);
     rhs[V_GAM + i] += Gs[i];
     if (P.shift == 1) {
       rhs[V_BETA + i] += (T)P.F * (T)src.center(V_B + i);
@@ -518,16 +521,16 @@ void launch_pair_t(int mode, int stage, const BssnArgs& a, hipStream_t s) {
 // CHEMORA_BSSN_SPLIT=0|1|2: 0 the fused single-plane kernel, 1 the split
 // pair, 2 the fused point code over the z-blocked staging in mixed
 // precision (the pair in FP64) (ablation switch, read at every launch).
-// Default, measured at 128^3: FP64 right-hand side alone the pair (0.743 ms
-// against 0.760 ms fused), FP64 RK4 substages the fused kernel (step 3.82 ms
-// against 3.90 ms: the pair's rest kernel also moves y_n and the
-// accumulator); mixed the z-blocked fused kernel (right-hand side 0.53 ms
-// against 0.59 ms, the pair 0.73 ms; RK4 step 2.89 ms against 3.15 ms).
+// Default, measured at 128^3: FP64 the pair (right-hand side 0.725 ms
+// against 0.760 ms fused; RK4 step 3.80 ms against 3.83 ms, the rest
+// kernel's stage updates included); mixed the z-blocked fused kernel
+// (right-hand side 0.53 ms against 0.59 ms, the pair 0.73 ms; RK4 step
+// 2.89 ms against 3.15 ms).
 int split_mode(int precision, int stage) {
+  (void)stage;
   const char* e = std::getenv("CHEMORA_BSSN_SPLIT");
   if (e && (e[0] == '0' || e[0] == '1' || e[0] == '2') && e[1] == 0) return e[0] - '0';
-  if (precision == CHEMORA_MIXED) return 2;
-  return stage == 0 ? 1 : 0;
+  return precision == CHEMORA_MIXED ? 2 : 1;
 }
 
 }  // namespace

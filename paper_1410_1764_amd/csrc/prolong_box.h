@@ -98,41 +98,86 @@ __device__ __forceinline__ void footprint(int q0, int q1, int n, int g, int& lo,
   cnt = min(floor_half(q1) + 3, n + g - 1) - lo + 1;
 }
 
-// value at fine coordinate q from coarse values src[(c - lo) * stride]:
-// the coincident value or the 6-point interpolant
-__device__ __forceinline__ double interp(const double* src, int stride, int q, int lo) {
-  if (q & 1) {
-    const double* p = src + (floor_half(q) - 2 - lo) * stride;
-    double acc = 0.0;
-#pragma unroll
-    for (int m = 0; m < 6; ++m) acc += kProlongW[m] * p[m * stride];
-    return acc;
+// Coordinates (x, y, z) of element e of a box with extents n0 x n1 x ...
+// (x fastest) that a thread visits at e = threadIdx.x, then every
+// blockDim.x elements.  The stride's own coordinates are computed once (the
+// same for the whole workgroup); each step then adds them with one carry per
+// axis instead of dividing e by the extents.
+struct Walk {
+  int x, y, z;     // coordinates of the current element
+  int dx, dy, dz;  // coordinates of the stride blockDim.x
+  int n0, n1;
+  __device__ __forceinline__ Walk(int e0, int n0_, int n1_) : n0(n0_), n1(n1_) {
+    const int s = (int)blockDim.x, r = e0 / n0, sr = s / n0;
+    x = e0 - r * n0;
+    y = r % n1;
+    z = r / n1;
+    dx = s - sr * n0;
+    dy = sr % n1;
+    dz = sr / n1;
   }
-  return src[(floor_half(q) - lo) * stride];
-}
+  // x + dx < 2 n0 and y + dy + 1 < 2 n1: one subtraction per axis suffices
+  __device__ __forceinline__ void step() {
+    x += dx;
+    const int cx = x >= n0;
+    x -= cx ? n0 : 0;
+    y += dy + cx;
+    const int cy = y >= n1;
+    y -= cy ? n1 : 0;
+    z += dz + cy;
+  }
+};
 
 // One pass: interpolate axis D of src (extents ext[0..2], x fastest) from its
 // coarse window (first coarse index c0[D]) to w[D] fine points starting at
-// fine coordinate q0[D]; ext[D] becomes w[D].  Output to LDS dst, or, when
-// dst is null, to the fine block at out (strides 1, sy, sz).
-template <int D>
+// fine coordinate q0[D]; ext[D] becomes w[D].  Output to LDS dst (LDS), or
+// to the fine block at out (strides 1, sy, sz).  A thread
+// takes two neighbouring fine points along D at a time: one coincident
+// (one coarse value) and one half-way (six), so that no lane of a wave
+// waits on the other kind's path; a box with odd w[D] ends in a single
+// point.  The half-way value sums the six weighted coarse values in order.
+template <int D, bool LDS>
 __device__ __forceinline__ void pass(const double* src, double* dst, int ext[3], const int w[3],
                                      const int q0[3], const int c0[3], double* out, long long sy,
                                      long long sz) {
   const int ne0 = D == 0 ? w[0] : ext[0], ne1 = D == 1 ? w[1] : ext[1];
   const int ne2 = D == 2 ? w[2] : ext[2];
-  const int n01 = ne0 * ne1, total = n01 * ne2;
-  const int st1 = ext[0], st2 = ext[0] * ext[1];
-  const int std_ = D == 0 ? 1 : (D == 1 ? st1 : st2);
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int z = e / n01, r = e - z * n01, y = r / ne0, x = r - y * ne0;
-    const int cd = D == 0 ? x : (D == 1 ? y : z);
-    const int base = (D == 0 ? 0 : x) + (D == 1 ? 0 : y) * st1 + (D == 2 ? 0 : z) * st2;
-    const double v = interp(src + base, std_, q0[D] + cd, c0[D]);
-    if (dst)
-      dst[e] = v;
-    else
-      out[x + y * sy + z * sz] = v;
+  // pairs along D
+  const int np0 = D == 0 ? (ne0 + 1) / 2 : ne0, np1 = D == 1 ? (ne1 + 1) / 2 : ne1;
+  const int np2 = D == 2 ? (ne2 + 1) / 2 : ne2;
+  const int total = np0 * np1 * np2;
+  const int st1 = ext[0], st2 = ext[0] * ext[1];  // source strides
+  const int sd = D == 0 ? 1 : (D == 1 ? st1 : st2);
+  const int o1 = ne0, o2 = ne0 * ne1;             // LDS output strides
+  const int od = D == 0 ? 1 : (D == 1 ? o1 : o2);
+  const long long gd = D == 0 ? 1 : (D == 1 ? sy : sz);
+  Walk p((int)threadIdx.x, np0, np1);
+  for (int e = threadIdx.x; e < total; e += blockDim.x, p.step()) {
+    const int i = 2 * (D == 0 ? p.x : (D == 1 ? p.y : p.z));  // first fine index along D
+    const int x = D == 0 ? i : p.x, y = D == 1 ? i : p.y, z = D == 2 ? i : p.z;
+    const double* s0 = src + (D == 0 ? 0 : x) + (D == 1 ? 0 : y) * st1 + (D == 2 ? 0 : z) * st2;
+    const int q = q0[D] + i;
+    const bool two = i + 1 < w[D];
+    const int qe = q + (q & 1), qo = q + 1 - (q & 1);  // the coincident and half-way point
+    // the coincident point lies inside the footprint even when it is past
+    // the box's last (half-way) point; the half-way point's six do not
+    const double ve = s0[(floor_half(qe) - c0[D]) * sd];
+    double vo = 0.0;
+    if ((q & 1) || two) {
+      const double* s6 = s0 + (floor_half(qo) - 2 - c0[D]) * sd;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) vo += kProlongW[m] * s6[m * sd];
+    }
+    const double v0 = (q & 1) ? vo : ve, v1 = (q & 1) ? ve : vo;
+    if constexpr (LDS) {
+      const int o = x + y * o1 + z * o2;
+      dst[o] = v0;
+      if (two) dst[o + od] = v1;
+    } else {
+      double* g = out + x + y * sy + z * sz;
+      g[0] = v0;
+      if (two) g[gd] = v1;
+    }
   }
   ext[D] = w[D];
 }
@@ -142,11 +187,11 @@ template <int D0, int D1, int D2>
 __device__ __forceinline__ void passes(double* A, double* B, int ext[3], const int w[3],
                                        const int q0[3], const int c0[3], double* out,
                                        long long sy, long long sz) {
-  pass<D0>(A, B, ext, w, q0, c0, nullptr, 0, 0);
+  pass<D0, true>(A, B, ext, w, q0, c0, nullptr, 0, 0);
   __syncthreads();
-  pass<D1>(B, A, ext, w, q0, c0, nullptr, 0, 0);
+  pass<D1, true>(B, A, ext, w, q0, c0, nullptr, 0, 0);
   __syncthreads();
-  pass<D2>(A, nullptr, ext, w, q0, c0, out, sy, sz);
+  pass<D2, false>(A, nullptr, ext, w, q0, c0, out, sy, sz);
 }
 
 // One box of fine ghost points: fine corner, extents, the segment it belongs
@@ -212,20 +257,20 @@ __device__ __forceinline__ void box_footprint(const Box& x, const Geo& C,
                                               int ntimes, double* A) {
   const long long corner = C.off0 + x.c0[0] + (long long)x.c0[1] * C.sy +
                            (long long)x.c0[2] * C.sz;
-  const int nxy = x.ext[0] * x.ext[1];
   const int step = kProlongU * (int)blockDim.x;
+  Walk p((int)threadIdx.x, x.ext[0], x.ext[1]);
   for (int e0 = (int)threadIdx.x; e0 < x.nfoot; e0 += step) {
     double ld[kProlongU][kMaxTimeLevels];
 #pragma unroll
     for (int u = 0; u < kProlongU; ++u) {
       const int e = e0 + u * (int)blockDim.x;
       if (e < x.nfoot) {
-        const int cz = e / nxy, r = e - cz * nxy, cy = r / x.ext[0], cx = r - cy * x.ext[0];
-        const long long o = corner + cx + (long long)cy * C.sy + (long long)cz * C.sz;
+        const long long o = corner + p.x + (long long)p.y * C.sy + (long long)p.z * C.sz;
 #pragma unroll
         for (int l = 0; l < kMaxTimeLevels; ++l)
           if (l < ntimes) ld[u][l] = lev[l][o];
       }
+      p.step();
     }
 #pragma unroll
     for (int u = 0; u < kProlongU; ++u) {
