@@ -47,7 +47,7 @@ BSSN_BYTES_PER_PT = 24 * 8 * 2       # read every variable once, write every rhs
 # 1,953 stencil + 2,295 pointwise operations at 4th order, 1+log,
 # Gamma-driver), stated beside the instruction-stream count.
 FLOPS_PER_POINT_EXPRESSION = 4248
-KERNEL_FP64 = "bssn_curv_kernel<double,KO_OFF> + bssn_rest_kernel<0,double,KO_OFF,8>"
+KERNEL_FP64 = "bssn_curv_kernel<double,KO_OFF,8,3> + bssn_rest_kernel<0,double,KO_OFF,8>"
 KERNEL_MIXED = "bssn_zfused_kernel<0,float,KO_OFF,8>"
 # Mixed precision runs unpacked FP32 (packed FP32 is disabled at compile
 # time), which issues at the FP64 vector rate: 256 CUs x 4 SIMDs x 16 lanes

@@ -383,23 +383,27 @@ __device__ __forceinline__ bool zblock(const BssnArgs& a, int& x0, int& y0, int&
   return true;
 }
 
-template <typename T, int KOM>
-__global__ void __launch_bounds__(kThreadsZ)
+template <typename T, int KOM, int TY, int NB>
+__global__ void __launch_bounds__(kTX * TY * kTZ)
 __attribute__((amdgpu_waves_per_eu(CHEMORA_SPLIT_WAVES))) bssn_curv_kernel(BssnArgs a) {
-  using S = ZShape<kTX, kTY, kTZ>;
-  __shared__ double L0[S::TOTAL], L1[S::TOTAL], L2[S::TOTAL];
-  __shared__ T stash[kStash * kThreadsZ];
+  using S = ZShape<kTX, TY, kTZ>;
+  constexpr int NT = kTX * TY * kTZ;
+  static_assert(NB == 2 || NB == 3, "two or three staging buffers");
+  // separate arrays: the compiler then knows that an asynchronous copy into
+  // one buffer cannot alias the reads of another, and does not wait for it
+  __shared__ double L0[S::TOTAL], L1[S::TOTAL], L2[NB == 3 ? S::TOTAL : 1];
+  __shared__ T stash[kStash * NT];
   double* const bufs[3] = {L0, L1, L2};
   const Geo& G = a.G;
   int x0, y0, k0, tx, ty, pz;
-  if (!zblock<kTY>(a, x0, y0, k0, tx, ty, pz)) return;  // whole workgroup: no barrier yet
+  if (!zblock<TY>(a, x0, y0, k0, tx, ty, pz)) return;  // whole workgroup: no barrier yet
   const int i = x0 + tx, j = y0 + ty, k = k0 + pz;
   const bool active = i < G.n[0] && j < G.n[1] && k < G.n[2];
-  ZSrc<kTX, kTY, kTZ, kZBufs, CurvOrder> src;
+  ZSrc<kTX, TY, kTZ, NB, CurvOrder> src;
   src.init(G, a.io.yin, bufs, x0, y0, k0, tx, ty, pz);
   double* o = (a.io.tmp ? a.io.tmp : a.io.out) + G.off0 +
               (active ? i + (long long)j * G.sy + (long long)k * G.sz : 0);
-  AdvStash<T, kThreadsZ> adv10{stash + threadIdx.x};
+  AdvStash<T, NT> adv10{stash + threadIdx.x};
   bssn_curv_point<T, KOM>(src, a.W, adv10, o, G.sv, active);
 }
 
@@ -481,6 +485,18 @@ int zty() {
   return (e && e[0] == '4' && e[1] == 0) ? 4 : 8;
 }
 
+// CHEMORA_CURV_TY=8|4: tile height of the curvature kernel (8, default:
+// 32 x 8 x 2 blocks, 512 threads, three staging buffers, one workgroup per
+// CU; 4: 32 x 4 x 2 blocks, 256 threads, two buffers, two workgroups per CU
+// whose barriers do not wait on each other, for more staging per point)
+// (ablation switch, read at every launch).  Measured at 128^3, FP64, same
+// job: right-hand side 0.720 ms (8) against 0.723 ms (4), RK4 step 3.79
+// against 3.81 ms.
+int curv_ty() {
+  const char* e = std::getenv("CHEMORA_CURV_TY");
+  return (e && e[0] == '4' && e[1] == 0) ? 4 : 8;
+}
+
 template <int STAGE, typename T, int TY>
 void launch_pair_ty(int mode, const BssnArgs& a0, hipStream_t s) {
   dim3 grid;
@@ -492,8 +508,14 @@ void launch_pair_ty(int mode, const BssnArgs& a0, hipStream_t s) {
       return;
     }
   }
-  const BssnArgs ac = zargs(a0, kTY, grid);
-  hipLaunchKernelGGL((bssn_curv_kernel<T, KO_OFF>), grid, dim3(kThreadsZ), 0, s, ac);
+  if (curv_ty() == 4) {
+    const BssnArgs ac = zargs(a0, 4, grid);
+    hipLaunchKernelGGL((bssn_curv_kernel<T, KO_OFF, 4, 2>), grid, dim3(kTX * 4 * kTZ), 0, s, ac);
+  } else {
+    const BssnArgs ac = zargs(a0, kTY, grid);
+    hipLaunchKernelGGL((bssn_curv_kernel<T, KO_OFF, kTY, kZBufs>), grid, dim3(kThreadsZ), 0, s,
+                       ac);
+  }
   const BssnArgs ar = zargs(a0, TY, grid);
   hipLaunchKernelGGL((bssn_rest_kernel<STAGE, T, KO_OFF, TY>), grid, dim3(kTX * TY * kTZ), 0, s,
                      ar);

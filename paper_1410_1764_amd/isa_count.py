@@ -105,7 +105,7 @@ def main():
     split = {}
     for name, body in kernel_bodies(_asm("bssn_split.hip")):
         c = count(body)
-        if "bssn_curv_kernelIdLi0E" in name:
+        if "bssn_curv_kernelIdLi0ELi8ELi3E" in name:
             split["fp64_curv"] = {"kernel": name, **c["f64"]}
         if "bssn_rest_kernelILi0EdLi0ELi8E" in name:
             split["fp64_rest"] = {"kernel": name, **c["f64"]}

@@ -10,7 +10,8 @@ kernel.  Cases: ragged grids that leave partial tiles in x and y and an odd
 number of planes (the last block's second plane idle), one wide enough for
 the XCD column walk (some workgroups get no tile), both gauges, both
 precisions, constraint enforcement, and RK4 steps, whose last substage keeps
-the intermediates in a stage buffer instead of the output."""
+the intermediates in a stage buffer instead of the output; the pair with
+other tile heights (32 x 4 x 2 and 32 x 8 x 2 for either kernel)."""
 import numpy as np
 import pytest
 import torch
@@ -56,6 +57,32 @@ def test_split_rhs_matches_oracle_and_fused(n, gauge, precision, mode, monkeypat
     assert e.max() <= TOL[precision]
     # same arithmetic in the same order: equal up to contraction choices
     assert ef.max() <= (1e-13 if precision == C.FP64 else 1e-5)
+
+
+@pytest.mark.parametrize("curv_ty,rest_ty", [("4", "8"), ("4", "4"), ("8", "4")])
+@pytest.mark.parametrize("precision", [C.FP64, C.MIXED])
+def test_split_tile_heights_bitwise(curv_ty, rest_ty, precision, monkeypatch):
+    """The pair with other tile heights (CHEMORA_CURV_TY, CHEMORA_SPLIT_TY)
+    evaluates every point with the same arithmetic: bitwise equal to the
+    default tiles, and within the bar of the oracle."""
+    n = (45, 27, 11)
+    h = tuple(1.0 / v for v in n)
+    gr, b = pair(n, 3, h, C.BSSN, precision=precision, **GAUGES["1+log/Gamma-driver"])
+    y0 = _smooth_random(n, 37)
+    st = gr.upload(y0)
+    gr.fill_ghosts(st)
+    monkeypatch.delenv("CHEMORA_CURV_TY", raising=False)
+    monkeypatch.delenv("CHEMORA_SPLIT_TY", raising=False)
+    default = _rhs(gr, st, 1, monkeypatch)
+    monkeypatch.setenv("CHEMORA_CURV_TY", curv_ty)
+    monkeypatch.setenv("CHEMORA_SPLIT_TY", rest_ty)
+    other = _rhs(gr, st, 1, monkeypatch)
+    yo = b.embed(y0)
+    oracle.fill_periodic(b, yo)
+    e = parity(other, b.interior(oracle.bssn_rhs(b, yo)))
+    print("tile heights", curv_ty, rest_ty, precision, "vs oracle", e.max(), flush=True)
+    assert np.array_equal(other, default)
+    assert e.max() <= TOL[precision]
 
 
 def test_split_rhs_minkowski_exactly_zero(monkeypatch):
