@@ -162,10 +162,10 @@ __device__ __forceinline__ void bssn_curv_point(Src& src, const Weights& w, Stas
   // K and At only enter from here on: loaded after the last grid function
   // is staged (no copy is in flight any more), so that they hold no
   // registers through the geometry
-  const T trK = (T)src.center(V_TRK);
+  const T trK = (T)src.center_nt(V_TRK);
   T At[6];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) At[q] = (T)src.center(V_AT + q);
+  for (int q = 0; q < 6; ++q) At[q] = (T)src.center_nt(V_AT + q);
 
   T Atm[3][3];
 #pragma unroll
@@ -244,13 +244,13 @@ __device__ __forceinline__ void bssn_rest_point(Src& src, const double* I, long 
   bool bpos[3];
   T beta[3];
   shift_at(src, bpos, beta);
-  const T chi = (T)src.center(V_CHI);
+  const T chi = (T)src.center_nt(V_CHI);
   const T trK = (T)src.center(V_TRK);
-  const T alpha = (T)src.center(V_ALP);
+  const T alpha = (T)src.center_nt(V_ALP);
   T gt[6], At[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    gt[q] = (T)src.center(V_GT + q);
+    gt[q] = (T)src.center_nt(V_GT + q);
     At[q] = (T)src.center(V_AT + q);
   }
   T Gs[3], Gd[3];

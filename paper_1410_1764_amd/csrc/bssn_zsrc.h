@@ -133,6 +133,11 @@ struct ZSrc {
   }
 
   __device__ __forceinline__ double center(int v) const { return Yc[v * sv]; }
+  // the centre value of a grid function this kernel does not stage: read once
+  // per point, so with a nontemporal load that does not displace staged lines
+  __device__ __forceinline__ double center_nt(int v) const {
+    return __builtin_nontemporal_load(&Yc[v * sv]);
+  }
 
   template <int YOUNGER>
   __device__ __forceinline__ void wait_and_sync() {
