@@ -44,7 +44,10 @@ __device__ __forceinline__ void tile_barrier() {
 }
 
 // Pointwise operands of one plane: rho at the point, and for the substage
-// update y_n (u, rho) and the accumulator (u, rho).
+// update y_n (u, rho) and the accumulator (u, rho).  y_n and the accumulator
+// are read once and the accumulator written once per substage, with
+// nontemporal loads and stores: they then do not displace the lines of u
+// that neighbouring workgroups' stencils still read from L2.
 struct Pointwise {
   double rho, u0, r0, au, ar;
 };
@@ -56,10 +59,10 @@ __device__ __forceinline__ Pointwise load_pointwise(const WaveArgs& a, long long
   w.rho = a.io.yin[G.off0 + p + G.sv];
   w.u0 = w.r0 = w.au = w.ar = 0.0;
   if (STAGE >= 2) {
-    w.u0 = a.io.y0[G.off0 + p];
-    w.r0 = a.io.y0[G.off0 + p + G.sv];
-    w.au = a.io.acc[G.off0 + p];
-    w.ar = a.io.acc[G.off0 + p + G.sv];
+    w.u0 = __builtin_nontemporal_load(&a.io.y0[G.off0 + p]);
+    w.r0 = __builtin_nontemporal_load(&a.io.y0[G.off0 + p + G.sv]);
+    w.au = __builtin_nontemporal_load(&a.io.acc[G.off0 + p]);
+    w.ar = __builtin_nontemporal_load(&a.io.acc[G.off0 + p + G.sv]);
   }
   return w;
 }
@@ -122,28 +125,33 @@ __global__ void __launch_bounds__(TX * TY) wave_stage_kernel(WaveArgs a) {
       const long long p = pk;
       double* out = a.io.out + G.off0;
       if (STAGE == 0) {
-        out[p] = ku;
-        out[p + G.sv] = kr;
+        __builtin_nontemporal_store(ku, &out[p]);
+        __builtin_nontemporal_store(kr, &out[p + G.sv]);
       } else {
         double* acc = a.io.acc + G.off0;
         const double u0 = STAGE == 1 ? c : cur.u0, r0 = STAGE == 1 ? cur.rho : cur.r0;
         double nu, nr;
         if (STAGE == 1) {
-          acc[p] = ku;
-          acc[p + G.sv] = kr;
+          __builtin_nontemporal_store(ku, &acc[p]);
+          __builtin_nontemporal_store(kr, &acc[p + G.sv]);
           nu = u0 + a.io.cdt * ku;
           nr = r0 + a.io.cdt * kr;
         } else if (STAGE == 2 || STAGE == 3) {
-          acc[p] = cur.au + 2.0 * ku;
-          acc[p + G.sv] = cur.ar + 2.0 * kr;
+          __builtin_nontemporal_store(cur.au + 2.0 * ku, &acc[p]);
+          __builtin_nontemporal_store(cur.ar + 2.0 * kr, &acc[p + G.sv]);
           nu = u0 + a.io.cdt * ku;
           nr = r0 + a.io.cdt * kr;
         } else {
           nu = u0 + a.io.cdt * (cur.au + ku);
           nr = r0 + a.io.cdt * (cur.ar + kr);
         }
-        store_with_images(out, G, i, j, k, nu, a.images);
-        store_with_images(out + G.sv, G, i, j, k, nr, a.images);
+        if (a.images) {
+          store_with_images(out, G, i, j, k, nu, true);
+          store_with_images(out + G.sv, G, i, j, k, nr, true);
+        } else {  // read by the next substage only after this launch: nontemporal
+          __builtin_nontemporal_store(nu, &out[p]);
+          __builtin_nontemporal_store(nr, &out[p + G.sv]);
+        }
       }
     }
     q0 = q1;

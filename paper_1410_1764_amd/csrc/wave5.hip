@@ -64,29 +64,36 @@ __global__ void __launch_bounds__(TX * TY) wave5_stage_kernel(W5Args a) {
     double* out = a.io.out + G.off0;
     if (STAGE == 0) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) out[p + v * sv] = kv[v];
+      for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(kv[v], &out[p + v * sv]);
     } else {
-      // every pointwise load before the first store (see bssn_store)
+      // every pointwise load before the first store (see bssn_store); y_n
+      // and the accumulator are read once and the accumulator written once
+      // per substage: nontemporal, so that they do not displace the stencil
+      // lines neighbouring workgroups still read
       double y0[5], ac[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        y0[v] = STAGE == 1 ? Y[p + v * sv] : a.io.y0[G.off0 + p + v * sv];
-        ac[v] = STAGE == 1 ? 0.0 : a.io.acc[G.off0 + p + v * sv];
+        y0[v] = STAGE == 1 ? Y[p + v * sv]
+                           : __builtin_nontemporal_load(&a.io.y0[G.off0 + p + v * sv]);
+        ac[v] = STAGE == 1 ? 0.0 : __builtin_nontemporal_load(&a.io.acc[G.off0 + p + v * sv]);
       }
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const long long q = p + v * sv;
         double nv;
         if (STAGE == 1) {
-          a.io.acc[G.off0 + q] = kv[v];
+          __builtin_nontemporal_store(kv[v], &a.io.acc[G.off0 + q]);
           nv = y0[v] + a.io.cdt * kv[v];
         } else if (STAGE == 2 || STAGE == 3) {
-          a.io.acc[G.off0 + q] = ac[v] + 2.0 * kv[v];
+          __builtin_nontemporal_store(ac[v] + 2.0 * kv[v], &a.io.acc[G.off0 + q]);
           nv = y0[v] + a.io.cdt * kv[v];
         } else {
           nv = y0[v] + a.io.cdt * (ac[v] + kv[v]);
         }
-        store_with_images(out + v * sv, G, i, j, k, nv, a.images != 0);
+        if (a.images)
+          store_with_images(out + v * sv, G, i, j, k, nv, true);
+        else  // read by the next substage only after this launch: nontemporal
+          __builtin_nontemporal_store(nv, &out[q]);
       }
     }
     r0 = r1;
