@@ -226,12 +226,10 @@ int chemora_fill_ghosts(chemora_grid* grid, double* state, double t, chemora_str
   }
 }
 
+// read at every chemora_rk4_step call, like the other ablation switches
 static bool periodic_images() {
-  static const bool v = [] {
-    const char* e = std::getenv("CHEMORA_PERIODIC");
-    return e && std::strcmp(e, "images") == 0;
-  }();
-  return v;
+  const char* e = std::getenv("CHEMORA_PERIODIC");
+  return e && std::strcmp(e, "images") == 0;
 }
 
 static hipError_t launch_stage(const chemora_grid* g, int stage, bool images, const StageIO& io,
