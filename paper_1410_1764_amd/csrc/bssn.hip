@@ -125,12 +125,12 @@ __global__ void __launch_bounds__(TX * TY) bssn_async_kernel(BssnArgs a) {
 
 // CHEMORA_BSSN_TILE=WxH forces the tile of the staged kernels (64x4, 32x8,
 // 16x16: 256 threads; 16x8: 128; 16x4, 8x8: 64), and a single width W the
-// tile W x (256 / W) (ablation switch)
+// tile W x (256 / W) (ablation switch, read at every launch)
 struct TileShape {
   int w, h;
 };
 TileShape forced_tile() {
-  static const TileShape t = [] {
+  const TileShape t = [] {
     const char* e = std::getenv("CHEMORA_BSSN_TILE");
     TileShape r{0, 0};
     if (!e) return r;
@@ -152,9 +152,10 @@ TileShape forced_tile() {
 // register-prefetched LDS staging: 0.766 / 0.641 ms).  Three buffers
 // (66 KB) let two mixed-precision workgroups share a CU, so the mixed
 // kernel (245 VGPRs) runs two waves per SIMD.
-// CHEMORA_BSSN_KERNEL=global|lds|async overrides it (ablation switch).
+// CHEMORA_BSSN_KERNEL=global|lds|async overrides it (ablation switch, read at
+// every launch).
 int kernel_override() {
-  static const int v = [] {
+  const int v = [] {
     const char* e = std::getenv("CHEMORA_BSSN_KERNEL");
     if (e && std::strcmp(e, "global") == 0) return 0;
     if (e && std::strcmp(e, "lds") == 0) return 1;
@@ -170,9 +171,9 @@ int kernel_variant(int precision) {
 }
 
 // CHEMORA_BSSN_NBUF=6: six staging buffers for the async 32x8 kernel
-// instead of three (ablation switch)
+// instead of three (ablation switch, read at every launch)
 int async_nbuf() {
-  static const int v = [] {
+  const int v = [] {
     const char* e = std::getenv("CHEMORA_BSSN_NBUF");
     return (e && std::atoi(e) == 6) ? 6 : 3;
   }();
@@ -180,9 +181,10 @@ int async_nbuf() {
 }
 
 // CHEMORA_BSSN_ORDER=plane restores the XCD-contiguous plane order of the
-// staged kernels instead of the column walk (ablation switch)
+// staged kernels instead of the column walk (ablation switch, read at every
+// launch)
 bool column_order() {
-  static const bool v = [] {
+  const bool v = [] {
     const char* e = std::getenv("CHEMORA_BSSN_ORDER");
     return !(e && std::strcmp(e, "plane") == 0);
   }();

@@ -266,16 +266,18 @@ __global__ void __launch_bounds__(CT) norms_kernel(const double* partial, int nb
 }
 
 // CHEMORA_CONS_NBUF=3|6: staging buffers of the staged kernel (3: two
-// workgroups fit a CU; ablation switch)
+// workgroups fit a CU; ablation switch, read at every launch)
 int cons_nbuf() {
-  static const int v = [] {
+  const int v = [] {
     const char* e = std::getenv("CHEMORA_CONS_NBUF");
     return (e && std::atoi(e) == 6) ? 6 : 3;
   }();
   return v;
 }
 
-// CHEMORA_CONS_KERNEL=global selects the cached-load kernel (ablation switch)
+// CHEMORA_CONS_KERNEL=global selects the cached-load kernel (ablation switch,
+// read once per process: it sets the number of workgroups, and with it the
+// size of the caller's partial-sum workspace)
 bool staged() {
   static const bool v = [] {
     const char* e = std::getenv("CHEMORA_CONS_KERNEL");

@@ -174,9 +174,10 @@ hipError_t launch_t(int stage, const WaveArgs& a, dim3 grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-// workgroups the z-split aims for (CHEMORA_WAVE_WGS overrides; ablation)
+// workgroups the z-split aims for (CHEMORA_WAVE_WGS overrides; ablation
+// switch, read at every launch)
 long long wave_workgroups() {
-  static const long long v = [] {
+  const long long v = [] {
     const char* e = std::getenv("CHEMORA_WAVE_WGS");
     const long long n = e ? std::atoll(e) : 0;
     return n >= 256 && n <= (1 << 20) ? n : 16384LL;
