@@ -130,12 +130,12 @@ struct Walk {
 
 // One pass: interpolate axis D of src (extents ext[0..2], x fastest) from its
 // coarse window (first coarse index c0[D]) to w[D] fine points starting at
-// fine coordinate q0[D]; ext[D] becomes w[D].  Output to LDS dst (LDS), or
-// to the fine block at out (strides 1, sy, sz).  A thread
-// takes two neighbouring fine points along D at a time: one coincident
-// (one coarse value) and one half-way (six), so that no lane of a wave
-// waits on the other kind's path; a box with odd w[D] ends in a single
-// point.  The half-way value sums the six weighted coarse values in order.
+// fine coordinate q0[D]; ext[D] becomes w[D].  Output to the LDS buffer dst
+// (LDS = true), or to the fine block at out (strides 1, sy, sz).  A thread
+// takes two neighbouring fine points along D at a time: one coincident (one
+// coarse value) and one half-way (six), so that no lane of a wave waits on
+// the other kind's path; a box with odd w[D] ends in a single point.  The
+// half-way value sums the six weighted coarse values in order.
 template <int D, bool LDS>
 __device__ __forceinline__ void pass(const double* src, double* dst, int ext[3], const int w[3],
                                      const int q0[3], const int c0[3], double* out, long long sy,
